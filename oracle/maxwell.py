@@ -1,0 +1,275 @@
+"""The two-substep ADI time step for Maxwell's equations (oracle, float64).
+
+Follows, in order:
+
+* section "Alternating directions splitting for Maxwell equations": the
+  curl split C1 - C2 and the two-substep scheme (eqs. scheme1a-scheme1d);
+* section "Variational formulation": weak forms weak1-weak4 and their
+  Kronecker-product discretisation discrete1-discrete4 with the block
+  matrices M, K1, K2, R1, R2, C1, C2 built from the 1D factors;
+* section "Incorporating non-regular material data ...": eq. dupa1ab (the
+  per-component systems), the three direction-wise 1D systems solved along
+  x, then y, then z, and the test-function-wise material (eq.
+  dupa1abcdefg and the equations after it).
+
+Readings (the paper is silent, ambiguous or misprinted):
+
+R1  Block (3,1) of C2 is printed as M(x)M(x)A; C2's third row is d/dx2 acting
+    on the first component (weak2 / weak4 / strong2), i.e. M(x)A(x)M.
+R2  discrete4 prints "+ tau/(2 mu) C1 E^{n+1}"; scheme1d / strong4 / weak4 all
+    give a minus sign.  The minus sign is used.
+R3  Boundary conditions (PEC: E x n = 0, H . n = 0) are imposed strongly:
+    E_c vanishes on the faces normal to the two other axes, H_c on the faces
+    normal to axis c.  The matching rows/columns of each 1D solve matrix are
+    identity rows/columns and the matching right-hand-side rows are zeroed.
+R4  Material is attached to test functions (rows): each degree of freedom
+    (i,j,k) takes (eps, mu, sigma) of the voxel containing its Greville
+    point, see ``sample_material``.
+R5  Conductivity and a current source are not in the paper.  They enter as
+    eps dE/dt + sigma E = curl H - J with sigma E averaged trapezoidally over
+    each half step and J evaluated at the half step's midpoint.  With
+    c = sigma tau / (4 eps) every E row is divided by (1 + c):
+        alpha = tau^2 / (4 eps mu (1 + c)),  beta = tau / (2 eps (1 + c)),
+        gamma = (1 - c) / (1 + c),           delta = tau / (2 mu).
+    sigma = 0 gives exactly the coefficients of discrete1-discrete4.
+R6  Order of the three 1D solves.  The paper lists the x, then y, then z
+    systems and, for a modified row of the second or third system, identifies
+    the already-solved (trial) indices with the test indices of the row.  Read
+    literally, that solves a product of per-line operators in which the
+    coefficient of a y- or z-modified row is taken at a *trial* x (and y)
+    index; that operator is not the row-scaled system of eq. dupa1ab and the
+    resulting scheme is violently unstable for piecewise-constant material
+    (spectral radius 1.3 per step for a two-material half space at
+    tau = h/2).  The appendix ("Varying coefficients ...", eq:split1 then
+    eq:split2) justifies linear cost by solving the coefficient-carrying
+    direction *first* and the unscaled direction afterwards, which is exact.
+    The oracle follows the appendix: for every E component the modified axis
+    is solved first, then the two remaining axes (shared matrices, which
+    commute) in x, y, z order.  The result is exactly the solution of the
+    row-scaled global Kronecker system of eq. dupa1ab; the H systems (no
+    material on the left) are solved x, then y, then z.
+R7  The 1D LU is pivot-free (see ``oracle.banded``).
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import Optional, Sequence
+
+import numpy as np
+
+from . import banded, bspline, gram
+
+# Right-hand sides of the E systems (dupa1ab; weak1 / weak3).  Each entry is
+# (coefficient, sign, source field, operator string XYZ), the operator being
+# X (x) Y (x) Z with X acting on x.  Fields: "E1".."E3", "H1".."H3".
+E_TERMS = {
+    1: (  # substep n -> n+1/2, eq. discrete1
+        [("gamma", +1, "E1", "MMM"), ("beta", +1, "H3", "MAM"), ("beta", -1, "H2", "MMA"),
+         ("alpha", +1, "E2", "ABM")],
+        [("gamma", +1, "E2", "MMM"), ("beta", +1, "H1", "MMA"), ("beta", -1, "H3", "AMM"),
+         ("alpha", +1, "E3", "MAB")],
+        [("gamma", +1, "E3", "MMM"), ("beta", +1, "H2", "AMM"), ("beta", -1, "H1", "MAM"),
+         ("alpha", +1, "E1", "BMA")],
+    ),
+    2: (  # substep n+1/2 -> n+1, eq. discrete3
+        [("gamma", +1, "E1", "MMM"), ("beta", +1, "H3", "MAM"), ("beta", -1, "H2", "MMA"),
+         ("alpha", +1, "E3", "AMB")],
+        [("gamma", +1, "E2", "MMM"), ("beta", +1, "H1", "MMA"), ("beta", -1, "H3", "AMM"),
+         ("alpha", +1, "E1", "BAM")],
+        [("gamma", +1, "E3", "MMM"), ("beta", +1, "H2", "AMM"), ("beta", -1, "H1", "MAM"),
+         ("alpha", +1, "E2", "MBA")],
+    ),
+}
+
+# Right-hand sides of the H systems (weak2 / weak4).  Fields with a prime
+# ("E1'") are the E components just computed in the same substep.
+H_TERMS = {
+    1: (  # eq. discrete2
+        [("one", +1, "H1", "MMM"), ("delta", -1, "E3", "MAM"), ("delta", +1, "E2'", "MMA")],
+        [("one", +1, "H2", "MMM"), ("delta", -1, "E1", "MMA"), ("delta", +1, "E3'", "AMM")],
+        [("one", +1, "H3", "MMM"), ("delta", -1, "E2", "AMM"), ("delta", +1, "E1'", "MAM")],
+    ),
+    2: (  # eq. discrete4 (with the sign of scheme1d, reading R2)
+        [("one", +1, "H1", "MMM"), ("delta", +1, "E2", "MMA"), ("delta", -1, "E3'", "MAM")],
+        [("one", +1, "H2", "MMM"), ("delta", +1, "E3", "AMM"), ("delta", -1, "E1'", "MMA")],
+        [("one", +1, "H3", "MMM"), ("delta", +1, "E1", "MAM"), ("delta", -1, "E2'", "AMM")],
+    ),
+}
+
+# Axis (0 = x, 1 = y, 2 = z) whose 1D system carries the stiffness term for
+# E_c: K1 = diag(MSM, MMS, SMM), K2 = diag(MMS, SMM, MSM).
+MOD_AXIS = {1: (1, 2, 0), 2: (2, 0, 1)}
+
+_NP_AXIS = (2, 1, 0)  # x, y, z -> numpy axis of a (nz, ny, nx) array
+
+
+def dirichlet_axes(kind: str, c: int):
+    """Axes (0=x,1=y,2=z) in which component c of E or H is constrained (R3)."""
+    if kind == "E":
+        return tuple(a for a in range(3) if a != c)
+    return (c,)
+
+
+def zero_boundary(R: np.ndarray, axes: Sequence[int]) -> np.ndarray:
+    R = R.copy()
+    for a in axes:
+        ax = _NP_AXIS[a]
+        idx = [slice(None)] * 3
+        for b in (0, R.shape[ax] - 1):
+            idx[ax] = b
+            R[tuple(idx)] = 0.0
+    return R
+
+
+def source_time(t, src) -> float:
+    """g(t) = sin(2 pi f0 (t - t0)) exp(-((t - t0)/w)^2) (not in the paper, R5)."""
+    s = t - src.t0
+    return float(np.sin(2.0 * np.pi * src.f0 * s) * np.exp(-(s / src.width) ** 2))
+
+
+def sample_material(N: int, p: int, eps_vox, mu_vox, sig_vox):
+    """Per-DOF (eps, mu, sigma) by Greville sampling of a voxel map (R4).
+
+    Voxel arrays are (Vz, Vy, Vx); DOF (i,j,k) takes the voxel that contains
+    (xi_i, xi_j, xi_k), voxel index min(floor(xi * V), V - 1) per axis.
+    """
+    knots = bspline.open_uniform_knots(N, p)
+    xi = bspline.greville(knots, p)
+    Vz, Vy, Vx = np.shape(eps_vox)
+    ix = np.minimum(np.floor(xi * Vx).astype(int), Vx - 1)
+    iy = np.minimum(np.floor(xi * Vy).astype(int), Vy - 1)
+    iz = np.minimum(np.floor(xi * Vz).astype(int), Vz - 1)
+    sel = np.ix_(iz, iy, ix)
+    return (np.asarray(eps_vox, float)[sel], np.asarray(mu_vox, float)[sel],
+            np.asarray(sig_vox, float)[sel])
+
+
+def coefficients(eps, mu, sig, dt):
+    """Per-row coefficients (R5); sigma = 0 reproduces discrete1-discrete4."""
+    c = sig * dt / (4.0 * eps)
+    alpha = dt * dt / (4.0 * eps * mu * (1.0 + c))
+    beta = dt / (2.0 * eps * (1.0 + c))
+    gamma = (1.0 - c) / (1.0 + c)
+    delta = dt / (2.0 * mu)
+    return {"alpha": alpha, "beta": beta, "gamma": gamma, "delta": delta}
+
+
+@dataclasses.dataclass
+class Problem:
+    """A patch of N^3 elements of degree p with per-DOF material and a step."""
+
+    N: int
+    p: int
+    eps: np.ndarray
+    mu: np.ndarray
+    sig: np.ndarray
+    dt: float
+    source: Optional[object] = None
+
+    def __post_init__(self):
+        self.n = self.N + self.p
+        shape = (self.n,) * 3
+        self.eps = np.broadcast_to(np.asarray(self.eps, float), shape).copy()
+        self.mu = np.broadcast_to(np.asarray(self.mu, float), shape).copy()
+        self.sig = np.broadcast_to(np.asarray(self.sig, float), shape).copy()
+        if np.any(self.eps <= 0) or np.any(self.mu <= 0) or np.any(self.sig < 0):
+            raise ValueError("need eps > 0, mu > 0, sigma >= 0")
+        self.M, self.S, self.A, self.B = gram.gram_matrices(self.N, self.p)
+        self.ops = {"M": self.M, "A": self.A, "B": self.B}
+        self.coef = coefficients(self.eps, self.mu, self.sig, self.dt)
+        self.coef["one"] = np.ones(shape)
+        self.knots = bspline.open_uniform_knots(self.N, self.p)
+
+    # -- building blocks ---------------------------------------------------
+    def apply(self, u: np.ndarray, ops: str) -> np.ndarray:
+        """(X (x) Y (x) Z) u for an operator string "XYZ"."""
+        X, Y, Z = (self.ops[o] for o in ops)
+        return banded.apply3(u, X, Y, Z, self.p)
+
+    def source_rows(self, c: int, t: float) -> np.ndarray:
+        """(J(t), V_rst) for component c: a g(t) B_r(xs) B_s(ys) B_t(zs)."""
+        out = np.zeros((self.n,) * 3)
+        src = self.source
+        if src is None or src.comp != c or src.amp == 0.0:
+            return out
+        bx = bspline.basis(self.knots, self.p, [src.xs[0]])[0]
+        by = bspline.basis(self.knots, self.p, [src.xs[1]])[0]
+        bz = bspline.basis(self.knots, self.p, [src.xs[2]])[0]
+        return src.amp * source_time(t, src) * np.einsum("k,j,i->kji", bz, by, bx)
+
+    def solve3(self, R: np.ndarray, kind: str, c: int, mod_axis: Optional[int]) -> np.ndarray:
+        """The three 1D solves of component c of E or H (reading R6 for the order).
+
+        With a modified axis the result is (X (x) Y (x) Z)^{-1} R with the
+        modified factor's rows carrying the per-test-function coefficient.
+        """
+        dax = dirichlet_axes(kind, c)
+        order = [0, 1, 2] if mod_axis is None else \
+            [mod_axis] + [a for a in range(3) if a != mod_axis]
+        u = R
+        for a in order:
+            if a == mod_axis:
+                u = banded.solve_axis(u, _NP_AXIS[a], self.M, self.p, stiff=self.S,
+                                      alpha=self.coef["alpha"], dirichlet=a in dax)
+            else:
+                u = banded.solve_axis(u, _NP_AXIS[a], self.M, self.p, dirichlet=a in dax)
+        return u
+
+    def rhs_E(self, sub: int, fields: dict, c: int, t_mid: float) -> np.ndarray:
+        R = np.zeros((self.n,) * 3)
+        for coef, sign, f, ops in E_TERMS[sub][c]:
+            R += sign * self.coef[coef] * self.apply(fields[f], ops)
+        R -= self.coef["beta"] * self.source_rows(c, t_mid)
+        return zero_boundary(R, dirichlet_axes("E", c))
+
+    def rhs_H(self, sub: int, fields: dict, c: int) -> np.ndarray:
+        R = np.zeros((self.n,) * 3)
+        for coef, sign, f, ops in H_TERMS[sub][c]:
+            R += sign * self.coef[coef] * self.apply(fields[f], ops)
+        return zero_boundary(R, dirichlet_axes("H", c))
+
+    def substep(self, sub: int, E, H, t: float):
+        """One substep (sub = 1: n -> n+1/2, sub = 2: n+1/2 -> n+1)."""
+        fields = {"E1": E[0], "E2": E[1], "E3": E[2], "H1": H[0], "H2": H[1], "H3": H[2]}
+        t_mid = t + (0.25 if sub == 1 else 0.75) * self.dt
+        En = []
+        for c in range(3):
+            R = self.rhs_E(sub, fields, c, t_mid)
+            En.append(self.solve3(R, "E", c, MOD_AXIS[sub][c]))
+        fields.update({"E1'": En[0], "E2'": En[1], "E3'": En[2]})
+        Hn = []
+        for c in range(3):
+            R = self.rhs_H(sub, fields, c)
+            Hn.append(self.solve3(R, "H", c, None))
+        return En, Hn
+
+    def step(self, E, H, t: float):
+        """One full time step n -> n+1; returns (E, H, t + dt)."""
+        E1, H1 = self.substep(1, E, H, t)
+        E2, H2 = self.substep(2, E1, H1, t)
+        return E2, H2, t + self.dt
+
+    def run(self, E, H, t: float, steps: int):
+        for _ in range(steps):
+            E, H, t = self.step(E, H, t)
+        return E, H, t
+
+    # -- state helpers -------------------------------------------------------
+    def constrain(self, E, H):
+        """Zero the constrained boundary coefficients of a state (R3)."""
+        return ([zero_boundary(E[c], dirichlet_axes("E", c)) for c in range(3)],
+                [zero_boundary(H[c], dirichlet_axes("H", c)) for c in range(3)])
+
+    def energy(self, E, H) -> float:
+        """Discrete energy sum_c (eps E_c, E_c) + (mu H_c, H_c), row-wise material."""
+        e = 0.0
+        for c in range(3):
+            e += float(np.sum(E[c] * self.eps * self.apply(E[c], "MMM")))
+            e += float(np.sum(H[c] * self.mu * self.apply(H[c], "MMM")))
+        return e
+
+
+def problem_from_voxels(N: int, p: int, material, dt: float, source=None) -> Problem:
+    """Problem with Greville-sampled voxel material (sigma non-dimensional)."""
+    eps, mu, sig = sample_material(N, p, material.eps_r, material.mu_r, material.sigma_nd)
+    return Problem(N, p, eps, mu, sig, dt, source)

@@ -1,0 +1,244 @@
+"""Pins of the oracle's banded LU, direction sweeps and full ADI step (CPU).
+
+The direction-wise solves are checked against dense Kronecker-product
+solves on tiny grids; the full step (constant material, with conductivity
+and a point source) against a dense solve of the block systems of eqs.
+discrete1-discrete4 assembled directly from the paper's block-matrix list
+(with the two misprints fixed as the oracle documents).
+"""
+import numpy as np
+import pytest
+from scipy.linalg import solve_banded
+
+from oracle import banded, bspline, gram, maxwell
+from workloads import DipoleSource, random_fields
+
+
+def kron3(X, Y, Z):
+    """Dense matrix of X (x) Y (x) Z on the [z][y][x] (x fastest) layout."""
+    return np.kron(Z, np.kron(Y, X))
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_band_lu_against_lapack(p):
+    rng = np.random.default_rng(0)
+    n = 23
+    A = np.zeros((n, n))
+    for d in range(-p, p + 1):
+        A += np.diag(rng.uniform(-1, 1, n - abs(d)), d)
+    A += np.diag(np.full(n, 2.0 * p + 2.0))
+    b = rng.standard_normal((n, 4))
+    L, U = banded.band_lu(banded.to_band(A, p)[:, :, None], p)
+    x = banded.band_lu_solve(L, U, b, p)
+    ab = np.zeros((2 * p + 1, n))
+    for i in range(n):
+        for j in range(max(0, i - p), min(n, i + p + 1)):
+            ab[p + i - j, j] = A[i, j]
+    np.testing.assert_allclose(x, solve_banded((p, p), ab, b), rtol=1e-13, atol=1e-13)
+    np.testing.assert_allclose(A @ x, b, atol=1e-12)
+
+
+@pytest.mark.parametrize("N,p", [(3, 2), (2, 3), (4, 1)])
+def test_constant_sweeps_equal_dense_kronecker_solve(N, p):
+    """solve[X,Y,Z] = (kron(Z, kron(Y, X)))^-1 rhs for shared 1D matrices."""
+    M, S, A, B = gram.gram_matrices(N, p)
+    n = N + p
+    rng = np.random.default_rng(1)
+    X = M + 0.3 * S
+    Y = gram.dirichlet(M)
+    Z = gram.dirichlet(M + 0.1 * S)
+    rhs = maxwell.zero_boundary(rng.standard_normal((n, n, n)), [1, 2])  # y, z constrained
+    u = rhs
+    u = banded.solve_axis(u, 2, M, p, stiff=S, alpha=np.full((n, n, n), 0.3))
+    u = banded.solve_axis(u, 1, M, p, dirichlet=True)
+    u = banded.solve_axis(u, 0, M, p, stiff=S, alpha=np.full((n, n, n), 0.1), dirichlet=True)
+    ref = np.linalg.solve(kron3(X, Y, Z), rhs.ravel()).reshape(n, n, n)
+    np.testing.assert_allclose(u, ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("c,sub", [(0, 1), (1, 1), (2, 1), (0, 2), (1, 2), (2, 2)])
+def test_modified_solve_equals_dense_row_scaled_kronecker(c, sub):
+    """Varying material: the E_c solve equals the dense solve of the row-scaled
+    global system of eq. dupa1ab, M..(M + diag(alpha) S)..M restricted to the
+    constrained space (reading R6: the modified axis is solved first)."""
+    N, p = 3, 2
+    M, S, _, _ = gram.gram_matrices(N, p)
+    n = N + p
+    rng = np.random.default_rng(2 + c)
+    eps = rng.uniform(1.0, 50.0, (n, n, n))
+    prob = maxwell.Problem(N, p, eps, 1.0, 0.0, 0.2)
+    alpha = prob.coef["alpha"]
+    mod = maxwell.MOD_AXIS[sub][c]
+    rhs = maxwell.zero_boundary(rng.standard_normal((n, n, n)), maxwell.dirichlet_axes("E", c))
+    u = prob.solve3(rhs, "E", c, mod)
+    mats = [M, M, M]
+    plain = kron3(*mats)
+    mats[mod] = S
+    stiff = kron3(*mats)
+    G = plain + alpha.ravel()[:, None] * stiff
+    free = _free_mask(n, "E")[c * n ** 3:(c + 1) * n ** 3]
+    ref = np.zeros(n ** 3)
+    ref[free] = np.linalg.solve(G[np.ix_(free, free)], rhs.ravel()[free])
+    np.testing.assert_allclose(u.ravel(), ref, rtol=1e-11, atol=1e-12 * np.abs(ref).max())
+
+
+# ---------------------------------------------------------------------------
+# Dense assembly of discrete1-discrete4 straight from the block-matrix list.
+
+def _blocks(M, S, A, B):
+    k = kron3
+    Z = np.zeros_like(k(M, M, M))
+    MMM = k(M, M, M)
+    blk = lambda rows: np.block(rows)
+    return dict(
+        M=blk([[MMM, Z, Z], [Z, MMM, Z], [Z, Z, MMM]]),
+        K1=blk([[k(M, S, M), Z, Z], [Z, k(M, M, S), Z], [Z, Z, k(S, M, M)]]),
+        K2=blk([[k(M, M, S), Z, Z], [Z, k(S, M, M), Z], [Z, Z, k(M, S, M)]]),
+        R1=blk([[Z, k(A, B, M), Z], [Z, Z, k(M, A, B)], [k(B, M, A), Z, Z]]),
+        R2=blk([[Z, Z, k(A, M, B)], [k(B, A, M), Z, Z], [Z, k(M, B, A), Z]]),
+        C1=blk([[Z, Z, k(M, A, M)], [k(M, M, A), Z, Z], [Z, k(A, M, M), Z]]),
+        # block (3,1) fixed to M (x) A (x) M (reading R1)
+        C2=blk([[Z, k(M, M, A), Z], [Z, Z, k(A, M, M)], [k(M, A, M), Z, Z]]),
+    )
+
+
+def _free_mask(n, kind):
+    """Boolean mask over the 3 n^3 unknowns of E or H that are not constrained."""
+    masks = []
+    for c in range(3):
+        m = np.ones((n, n, n), bool)
+        for a in maxwell.dirichlet_axes(kind, c):
+            ax = maxwell._NP_AXIS[a]
+            idx = [slice(None)] * 3
+            for b in (0, n - 1):
+                idx[ax] = b
+                m[tuple(idx)] = False
+        masks.append(m.ravel())
+    return np.concatenate(masks)
+
+
+def _dense_step(N, p, eps, mu, sig, dt, src, E, H, t):
+    """One step from the dense block systems; eps, mu, sig scalars or per-DOF
+    arrays (material attached to test functions = rows, reading R4/R5)."""
+    M, S, A, B = gram.gram_matrices(N, p)
+    n = N + p
+    K = _blocks(M, S, A, B)
+    C = K["C1"] - K["C2"]
+    full = lambda v: np.tile(np.broadcast_to(np.asarray(v, float), (n, n, n)).ravel(), 3)
+    eps, mu, sig = full(eps), full(mu), full(sig)
+    c = sig * dt / (4 * eps)
+    a = dt * dt / (4 * eps * mu * (1 + c))
+    b = dt / (2 * eps * (1 + c))
+    g = (1 - c) / (1 + c)
+    d = dt / (2 * mu)
+    fe, fh = _free_mask(n, "E"), _free_mask(n, "H")
+    knots = bspline.open_uniform_knots(N, p)
+
+    def J(tt):
+        v = np.zeros(3 * n ** 3)
+        if src is not None:
+            bx, by, bz = (bspline.basis(knots, p, [s])[0] for s in src.xs)
+            g_t = np.sin(2 * np.pi * src.f0 * (tt - src.t0)) * np.exp(-((tt - src.t0) / src.width) ** 2)
+            v[src.comp * n ** 3:(src.comp + 1) * n ** 3] = src.amp * g_t * np.einsum(
+                "k,j,i->kji", bz, by, bx).ravel()
+        return v
+
+    def solve(Mat, rhs, free):
+        x = np.zeros_like(rhs)
+        x[free] = np.linalg.solve(Mat[np.ix_(free, free)], rhs[free])
+        return x
+
+    e, h = np.concatenate([x.ravel() for x in E]), np.concatenate([x.ravel() for x in H])
+    # discrete1 (with conductivity and source, reading R5)
+    e1 = solve(K["M"] + a[:, None] * K["K1"], g * (K["M"] @ e) + b * (C @ h)
+               + a * (K["R1"] @ e) - b * J(t + dt / 4), fe)
+    # discrete2
+    h1 = solve(K["M"], K["M"] @ h - d * (K["C1"] @ e) + d * (K["C2"] @ e1), fh)
+    # discrete3
+    e2 = solve(K["M"] + a[:, None] * K["K2"], g * (K["M"] @ e1) + b * (C @ h1)
+               + a * (K["R2"] @ e1) - b * J(t + 3 * dt / 4), fe)
+    # discrete4 with the sign of scheme1d (reading R2)
+    h2 = solve(K["M"], K["M"] @ h1 + d * (K["C2"] @ e1) - d * (K["C1"] @ e2), fh)
+    sh = (n, n, n)
+    return ([x.reshape(sh) for x in np.split(e2, 3)], [x.reshape(sh) for x in np.split(h2, 3)])
+
+
+@pytest.mark.parametrize("N,p,eps,mu,sig,dt,with_src", [
+    (2, 2, 1.0, 1.0, 0.0, 0.1, False),
+    (3, 2, 2.5, 1.3, 0.0, 0.07, True),
+    (2, 3, 4.0, 0.7, 3.0, 0.2, True),
+    (3, 1, 1.0, 2.0, 10.0, 0.05, False),
+    (3, 2, "rand", "rand", "rand", 0.1, True),
+    (2, 3, "rand", 1.0, "rand", 0.3, True),
+])
+def test_full_step_equals_dense_block_solve(N, p, eps, mu, sig, dt, with_src):
+    n = N + p
+    rng = np.random.default_rng(17)
+    rnd = lambda v, lo, hi: rng.uniform(lo, hi, (n, n, n)) if v == "rand" else v
+    eps, mu, sig = rnd(eps, 1.0, 50.0), rnd(mu, 0.5, 2.0), rnd(sig, 0.0, 20.0)
+    src = DipoleSource(xs=(0.41, 0.55, 0.37), comp=1, amp=0.8, f0=1.5, t0=0.1, width=0.3) \
+        if with_src else None
+    prob = maxwell.Problem(N, p, eps, mu, sig, dt, src)
+    F = random_fields(n, seed=5)
+    E, H = prob.constrain(list(F[:3]), list(F[3:]))
+    t = 0.03
+    E1, H1, t1 = prob.step(E, H, t)
+    Ed, Hd = _dense_step(N, p, eps, mu, sig, dt, src, E, H, t)
+    for a, b_ in zip(E1 + H1, Ed + Hd):
+        np.testing.assert_allclose(a, b_, rtol=1e-11, atol=1e-12 * max(1.0, np.abs(b_).max()))
+    assert t1 == pytest.approx(t + dt)
+
+
+def test_rhs_rows_with_varying_material_equal_dense_row_scaling():
+    """E and H right-hand sides with per-row (test function) coefficients."""
+    N, p = 3, 2
+    n = N + p
+    rng = np.random.default_rng(7)
+    eps = rng.uniform(1, 50, (n, n, n))
+    mu = rng.uniform(0.5, 2, (n, n, n))
+    sig = rng.uniform(0, 20, (n, n, n))
+    dt = 0.05
+    prob = maxwell.Problem(N, p, eps, mu, sig, dt)
+    M, S, A, B = gram.gram_matrices(N, p)
+    K = _blocks(M, S, A, B)
+    F = random_fields(n, seed=8)
+    E, H = prob.constrain(list(F[:3]), list(F[3:]))
+    e, h = np.concatenate([x.ravel() for x in E]), np.concatenate([x.ravel() for x in H])
+    co = prob.coef
+    rep = lambda v: np.tile(v.ravel(), 3)
+    dense = rep(co["gamma"]) * (K["M"] @ e) + rep(co["beta"]) * ((K["C1"] - K["C2"]) @ h) \
+        + rep(co["alpha"]) * (K["R1"] @ e)
+    fe = _free_mask(n, "E")
+    dense[~fe] = 0.0
+    fields = {"E1": E[0], "E2": E[1], "E3": E[2], "H1": H[0], "H2": H[1], "H3": H[2]}
+    mine = np.concatenate([prob.rhs_E(1, fields, c, 0.0).ravel() for c in range(3)])
+    np.testing.assert_allclose(mine, dense, rtol=1e-12, atol=1e-13 * np.abs(dense).max())
+
+
+def test_source_rows_partition_of_unity():
+    N, p = 6, 3
+    src = DipoleSource(xs=(0.3, 0.61, 0.5), comp=2, amp=1.7, f0=2.0, t0=0.0, width=1e9)
+    prob = maxwell.Problem(N, p, 1.0, 1.0, 0.0, 0.1, src)
+    t = 1.0 / 8.0  # sin(2 pi 2 t) = 1, exp(0) = 1
+    rows = prob.source_rows(2, t)
+    assert rows.sum() == pytest.approx(1.7, rel=1e-13)
+    assert np.count_nonzero(rows) <= (p + 1) ** 3
+    assert np.all(prob.source_rows(0, t) == 0)
+
+
+def test_material_greville_sampling_bruteforce():
+    N, p, V = 5, 2, 7
+    rng = np.random.default_rng(3)
+    vox = rng.uniform(1, 2, (V, V, V))
+    eps, _, _ = maxwell.sample_material(N, p, vox, vox, vox)
+    knots = bspline.open_uniform_knots(N, p)
+    xi = bspline.greville(knots, p)
+    n = N + p
+    for k in range(n):
+        for j in range(n):
+            for i in range(n):
+                # brute force: first voxel whose box [v/V, (v+1)/V] contains the point
+                vi = [next(v for v in range(V) if v / V <= c <= (v + 1) / V and
+                           not (c == (v + 1) / V and v + 1 < V))
+                      for c in (xi[i], xi[j], xi[k])]
+                assert eps[k, j, i] == vox[vi[2], vi[1], vi[0]]
