@@ -1,0 +1,155 @@
+/*
+ * adimx -- ADI isogeometric time stepping of Maxwell's equations on AMD MI355X.
+ *
+ * C ABI of libadimx.so.  Every function is extern "C", never throws and
+ * returns an int status (ADI_OK = 0 or a negative ADI_E* code) unless stated.
+ * After an error the context stays usable and adi_last_error() returns a
+ * message.  All host arrays are copied before the call returns; the caller
+ * keeps ownership of everything it passes in.  Device memory is either
+ * allocated by the library or carved from a caller-owned workspace bound
+ * with adi_bind_workspace (that workspace must outlive the context).
+ *
+ * Method (Paszynski, Los, Munoz-Matute, arXiv 2103.06998):
+ *   domain (0,1)^3, N^3 uniform elements, degree-p B-splines of continuity
+ *   C^{p-1} on open uniform knots, n = N + p coefficients per axis and field
+ *   component; E and H each have three components (section "Alternating
+ *   directions splitting for Maxwell equations").  One time step is two
+ *   substeps (eqs. scheme1a-scheme1d, discretised as discrete1-discrete4):
+ *   a sum-factorised right-hand side, then three direction-wise banded
+ *   (bandwidth 2p+1) line solves per component, with the material attached
+ *   to test functions (section "Incorporating non-regular material data").
+ *
+ * Layout of every field array at this boundary: six components
+ * [E1,E2,E3,H1,H2,H3], each n^3 float64 in [z][y][x] order with x fastest
+ * (the paper's reordering of each right-hand side into N_x rows).
+ */
+#ifndef ADIMX_H
+#define ADIMX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct adi_ctx adi_ctx;
+
+enum {
+  ADI_OK = 0,
+  ADI_EINVAL = -1,     /* bad handle, size, mode or material value            */
+  ADI_ENOMEM = -2,     /* device allocation or workspace too small            */
+  ADI_EHIP = -3,       /* a HIP runtime call failed (message kept)            */
+  ADI_ESINGULAR = -4,  /* a pivot of a 1D factorisation is (numerically) zero */
+  ADI_ENONFINITE = -5, /* NaN / Inf in an input                               */
+  ADI_ESTATE = -6      /* call out of order (e.g. step before factor)         */
+};
+
+enum {
+  ADI_FP64 = 0,        /* fields, right-hand sides and sweeps in float64     */
+  ADI_FP32_REFINE = 1  /* float32 bulk, float64 factors, one float64 residual
+                          correction per E solve                              */
+};
+
+enum { ADI_MAP_GREVILLE = 0 };
+
+/*
+ * Create a context for an N x N x N element patch of degree p (1 <= p <= 4,
+ * N >= 1; only cubic patches nx = ny = nz are supported) on HIP stream
+ * `hip_stream` (a hipStream_t, NULL = the null stream).  Nothing is
+ * allocated on the device until adi_factor.  *out receives the handle.
+ */
+int adi_create(adi_ctx** out, int nx, int ny, int nz, int p, int precision, void* hip_stream);
+
+/* Number of coefficients per axis (N + p). */
+int adi_ncoef(const adi_ctx* ctx);
+
+/*
+ * Bytes of device memory the context needs once factored (fields, scratch,
+ * coefficients, per-line factors).  A caller that wants to own the memory
+ * (e.g. a PyTorch tensor) allocates this many bytes, 256-byte aligned, and
+ * binds it before adi_factor.  Returns 0 for an invalid handle.
+ */
+size_t adi_workspace_bytes(const adi_ctx* ctx);
+int adi_bind_workspace(adi_ctx* ctx, void* dev_ptr, size_t bytes);
+
+/*
+ * Material given as a voxel map (vx, vy, vz voxels, x fastest, float64):
+ * relative permittivity, relative permeability and the non-dimensional
+ * conductivity sigma_nd = Z0 L sigma.  Each degree of freedom takes the
+ * voxel containing the Greville point of its test function (material is
+ * attached to test functions, eq. dupa1abcdefg and the text around it).
+ * EINVAL if eps <= 0, mu <= 0, sigma < 0 or a value is not finite.
+ */
+int adi_set_material(adi_ctx* ctx, const double* eps_r, const double* mu_r,
+                     const double* sigma_nd, int vx, int vy, int vz, int map_mode);
+
+/* Material given directly per degree of freedom (three n^3 arrays, x fastest). */
+int adi_set_material_dof(adi_ctx* ctx, const double* eps, const double* mu, const double* sigma_nd);
+
+/*
+ * Build the 1D Gram matrices M, S, A, B (float64, exact Gauss quadrature),
+ * the per-row coefficients for time step dt (alpha, beta, gamma, delta) and
+ * the pivot-free banded LU factors, in float64: shared factors of the
+ * unmodified 1D matrices and per-line factors of the material-modified
+ * ones.  ESINGULAR if a pivot is below 1e-14 times its diagonal entry.
+ * ESTATE if no material was set.
+ */
+int adi_factor(adi_ctx* ctx, double dt);
+
+/*
+ * Point dipole source J = amp g(t) e_comp delta(x - xs) with
+ * g(t) = sin(2 pi f0 (t - t0)) exp(-((t - t0)/width)^2); it enters each E
+ * right-hand side as -beta (J(t_mid), V) at the midpoint of the substep.
+ * amp = 0 removes the source.  Must be called before adi_factor or
+ * adi_factor must be called again afterwards.
+ */
+int adi_set_source(adi_ctx* ctx, const double xs[3], int comp, double amp, double f0,
+                   double t0, double width);
+
+/* Upload a state (6 n^3 float64, layout above) and set the time t. */
+int adi_set_fields(adi_ctx* ctx, const double* EH, double t);
+
+/*
+ * Enqueue nsteps full time steps on the context's stream and return without
+ * waiting.  Each step is one replay of a captured HIP graph.
+ */
+int adi_step(adi_ctx* ctx, int nsteps);
+
+/* Wait for the stream, then copy the state to EH_out (float64) and t to *t_out. */
+int adi_get_fields(adi_ctx* ctx, double* EH_out, double* t_out);
+
+/*
+ * Device pointer of the current state (6 n^3 contiguous values of dtype
+ * *dtype: 0 = float64, 1 = float32) for zero-copy access.  Valid until the
+ * next adi_step / adi_set_fields / adi_destroy.
+ */
+int adi_fields_device(adi_ctx* ctx, void** dev, int* dtype);
+
+/* Wait for all work enqueued by the context. */
+int adi_sync(adi_ctx* ctx);
+
+const char* adi_last_error(const adi_ctx* ctx);
+void adi_destroy(adi_ctx* ctx);
+
+/*
+ * Single hot-path stages on host buffers (float64 in and out), for testing
+ * one step of the method against a reference.  Each runs the same kernels as
+ * adi_step and synchronises.
+ *
+ * adi_rhs: right-hand sides of one stage.  stage 0 = E (eqs. discrete1 /
+ *   discrete3: in = [E1,E2,E3,H1,H2,H3], t = time at the start of the
+ *   substep), stage 1 = H (eqs. discrete2 / discrete4: in = [H1,H2,H3,
+ *   E_old1..3, E_new1..3]); sub = 1 or 2.  out receives 3 n^3 values with
+ *   the constrained boundary rows zeroed.
+ * adi_solve: the three 1D solves of one stage applied to 3 n^3 right-hand
+ *   sides in place (E: modified axis first, then the other two; H: x, y, z).
+ */
+int adi_rhs(adi_ctx* ctx, int stage, int sub, const double* in, double t, double* out);
+int adi_solve(adi_ctx* ctx, int stage, int sub, double* inout);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ADIMX_H */

@@ -1,0 +1,75 @@
+"""ctypes declarations of the libadimx C ABI (include/adimx.h).
+
+Argument marshalling only: every step of the computation runs in the
+library's HIP kernels.  Loading fails loudly if the library is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libadimx.so")
+
+ADI_OK, ADI_EINVAL, ADI_ENOMEM, ADI_EHIP, ADI_ESINGULAR, ADI_ENONFINITE, ADI_ESTATE = \
+    0, -1, -2, -3, -4, -5, -6
+ADI_FP64, ADI_FP32_REFINE = 0, 1
+ADI_MAP_GREVILLE = 0
+
+STATUS_NAMES = {0: "ADI_OK", -1: "ADI_EINVAL", -2: "ADI_ENOMEM", -3: "ADI_EHIP",
+                -4: "ADI_ESINGULAR", -5: "ADI_ENONFINITE", -6: "ADI_ESTATE"}
+
+# Every exported symbol and its (restype, argtypes).
+_P = ctypes.c_void_p
+_D = ctypes.POINTER(ctypes.c_double)
+_I = ctypes.c_int
+SIGNATURES = {
+    "adi_create": (_I, [ctypes.POINTER(_P), _I, _I, _I, _I, _I, _P]),
+    "adi_ncoef": (_I, [_P]),
+    "adi_workspace_bytes": (ctypes.c_size_t, [_P]),
+    "adi_bind_workspace": (_I, [_P, _P, ctypes.c_size_t]),
+    "adi_set_material": (_I, [_P, _D, _D, _D, _I, _I, _I, _I]),
+    "adi_set_material_dof": (_I, [_P, _D, _D, _D]),
+    "adi_factor": (_I, [_P, ctypes.c_double]),
+    "adi_set_source": (_I, [_P, _D, _I, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                            ctypes.c_double]),
+    "adi_set_fields": (_I, [_P, _D, ctypes.c_double]),
+    "adi_step": (_I, [_P, _I]),
+    "adi_get_fields": (_I, [_P, _D, _D]),
+    "adi_fields_device": (_I, [_P, ctypes.POINTER(_P), ctypes.POINTER(_I)]),
+    "adi_sync": (_I, [_P]),
+    "adi_last_error": (ctypes.c_char_p, [_P]),
+    "adi_destroy": (None, [_P]),
+    "adi_rhs": (_I, [_P, _I, _I, _D, ctypes.c_double, _D]),
+    "adi_solve": (_I, [_P, _I, _I, _D]),
+}
+
+_lib = None
+
+
+class AdiError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libadimx.so (cached).  Raises ImportError if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with "
+                          "`python -m paper_2103_06998_amd.build` (there is no fallback)")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def dptr(a):
+    """ctypes double* of a C-contiguous float64 numpy array."""
+    return a.ctypes.data_as(_D)

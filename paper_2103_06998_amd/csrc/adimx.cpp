@@ -1,0 +1,746 @@
+// Host driver of libadimx: context, device workspace, initialisation
+// (Gram matrices, coefficients, factorisations) and the captured time step.
+//
+// One time step (eqs. scheme1a-scheme1d / discrete1-discrete4) is, per
+// substep s = 1, 2:
+//   E stage: right-hand sides of E1, E2, E3 (one kernel), then for every
+//            component its three 1D solves, the material-modified axis first
+//            (that order solves the row-scaled system of eq. dupa1ab
+//            exactly; the remaining two axes have shared factors);
+//   H stage: right-hand sides of H1, H2, H3, then mass solves along x, y, z.
+// In ADI_FP32_REFINE mode the E stage is followed by a float64 residual of
+// the float32 solve and one correction solve.
+#include "adimx.h"
+#include "adimx_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace adimx;
+
+namespace {
+
+// Axis carrying the stiffness term of E_c (K1 = diag(MSM, MMS, SMM) in
+// substep 1, K2 = diag(MMS, SMM, MSM) in substep 2); 0 = x, 1 = y, 2 = z.
+constexpr int kModAxis[2][3] = {{1, 2, 0}, {2, 0, 1}};
+
+bool dirichlet(int kindH, int c, int axis) {
+  // PEC: E_c vanishes on the faces normal to the other axes, H_c on the faces
+  // normal to axis c.
+  return kindH ? (axis == c) : (axis != c);
+}
+
+struct Region {
+  size_t off, bytes;
+};
+
+}  // namespace
+
+struct adi_ctx {
+  int N = 0, p = 0, n = 0, prec = ADI_FP64;
+  size_t D = 0;            // n^3
+  size_t esz = 8;          // bytes per field element
+  hipStream_t stream = nullptr;
+  hipStream_t cap = nullptr;
+  std::string err;
+
+  std::vector<double> eps, mu, sig;
+  bool have_material = false;
+  SourceArgs src;
+  double src_xs[3] = {0.5, 0.5, 0.5};
+
+  double dt = 0.0, t = 0.0;
+  bool factored = false;
+
+  unsigned char* ws = nullptr;
+  size_t ws_bytes = 0;
+  bool own_ws = false;
+
+  // device pointers (into ws)
+  void* B[4] = {};          // 4 field buffers of 3 D elements; B0|B1 = state (E|H)
+  void* coefT[4] = {};      // alpha, beta, gamma, delta in the field type
+  double* coef64[4] = {};   // float64 copies (refine mode), else alias of coefT
+  void* bandT = nullptr;    // [M,A,B,S][n][2p+1] in the field type
+  double* band64 = nullptr; // same in float64
+  double* fb64 = nullptr;   // factor bands: Mdir, Sdir (n (2p+1) each)
+  void* shL[2] = {}, *shU[2] = {}, *shD[2] = {};  // shared factors: [0] free, [1] Dirichlet
+  void* mL[6] = {}, *mU[6] = {}, *mD[6] = {};     // per-line factors, system (s-1)*3 + c
+  double* minratio = nullptr;
+  double* d_t = nullptr;
+  float* R32 = nullptr;     // residual scratch (refine mode), 3 D
+
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+
+  bool refine() const { return prec == ADI_FP32_REFINE; }
+};
+
+namespace {
+
+int fail(adi_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+#define HIPCHK(ctx, expr)                                                           \
+  do {                                                                              \
+    hipError_t e_ = (expr);                                                         \
+    if (e_ != hipSuccess)                                                           \
+      return fail(ctx, ADI_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// Walk the workspace layout; if `base` is non-null assign the pointers.
+size_t layout(adi_ctx* c, unsigned char* base) {
+  size_t cur = 0;
+  auto take = [&](size_t bytes) -> unsigned char* {
+    cur = (cur + 255) & ~size_t(255);
+    unsigned char* ptr = base ? base + cur : nullptr;
+    cur += bytes;
+    return ptr;
+  };
+  const size_t D = c->D, es = c->esz;
+  const int n = c->n, W = 2 * c->p + 1, P = c->p;
+  // B0..B3 contiguous so that B0|B1 (the state) is one 6 D array
+  unsigned char* b = take(4 * 3 * D * es);
+  for (int i = 0; i < 4; ++i) c->B[i] = b ? b + size_t(i) * 3 * D * es : nullptr;
+  for (int i = 0; i < 4; ++i) c->coefT[i] = take(D * es);
+  for (int i = 0; i < 4; ++i)
+    c->coef64[i] = c->refine() ? reinterpret_cast<double*>(take(D * 8))
+                               : reinterpret_cast<double*>(c->coefT[i]);
+  c->bandT = take(size_t(4) * n * W * es);
+  c->band64 = reinterpret_cast<double*>(take(size_t(4) * n * W * 8));
+  c->fb64 = reinterpret_cast<double*>(take(size_t(2) * n * W * 8));
+  for (int v = 0; v < 2; ++v) {
+    c->shL[v] = take(size_t(n) * P * es);
+    c->shU[v] = take(size_t(n) * P * es);
+    c->shD[v] = take(size_t(n) * es);
+  }
+  for (int s = 0; s < 6; ++s) {
+    c->mL[s] = take(size_t(P) * D * es);
+    c->mU[s] = take(size_t(P) * D * es);
+    c->mD[s] = take(D * es);
+  }
+  c->minratio = reinterpret_cast<double*>(take(size_t(n) * n * 8));
+  c->d_t = reinterpret_cast<double*>(take(8));
+  c->R32 = c->refine() ? reinterpret_cast<float*>(take(3 * D * 4)) : nullptr;
+  return cur + 256;
+}
+
+void* comp(void* buf, int c, const adi_ctx* x) {
+  return static_cast<unsigned char*>(buf) + size_t(c) * x->D * x->esz;
+}
+
+template <typename T>
+std::vector<T> cast_vec(const std::vector<double>& v) {
+  return std::vector<T>(v.begin(), v.end());
+}
+
+int upload(adi_ctx* c, void* dst, const std::vector<double>& src) {
+  if (c->esz == 8) {
+    HIPCHK(c, hipMemcpy(dst, src.data(), src.size() * 8, hipMemcpyHostToDevice));
+  } else {
+    std::vector<float> f = cast_vec<float>(src);
+    HIPCHK(c, hipMemcpy(dst, f.data(), f.size() * 4, hipMemcpyHostToDevice));
+  }
+  return ADI_OK;
+}
+
+// ---------------------------------------------------------------- enqueue
+template <typename T>
+RhsArgs<T> rhs_args(adi_ctx* c, const void* const* f, int nf, void* const* out, int kindH,
+                    int sub) {
+  RhsArgs<T> a{};
+  for (int i = 0; i < nf; ++i) a.f[i] = f[i];
+  for (int i = 0; i < 3; ++i) a.out[i] = out[i];
+  if (kindH) {
+    a.coef[0] = static_cast<const T*>(c->coefT[3]);
+  } else {
+    a.coef[0] = static_cast<const T*>(c->coefT[2]);  // gamma
+    a.coef[1] = static_cast<const T*>(c->coefT[1]);  // beta
+    a.coef[2] = static_cast<const T*>(c->coefT[0]);  // alpha
+  }
+  a.band = static_cast<const T*>(c->bandT);
+  a.n = c->n;
+  a.zchunk = 32;
+  a.src = c->src;
+  a.tnow = c->d_t;
+  a.frac_dt = (sub == 1 ? 0.25 : 0.75) * c->dt;
+  return a;
+}
+
+SweepDesc desc_for(adi_ctx* c, int kindH, int sub, int comp_i, int axis, void* in, void* out,
+                   const void* acc) {
+  SweepDesc d{};
+  d.axis = axis;
+  d.in = in;
+  d.out = out;
+  d.acc = acc;
+  const bool mod = !kindH && kModAxis[sub - 1][comp_i] == axis;
+  if (mod) {
+    const int s = (sub - 1) * 3 + comp_i;
+    d.L = c->mL[s];
+    d.U = c->mU[s];
+    d.D = c->mD[s];
+    d.modified = 1;
+  } else {
+    const int v = dirichlet(kindH, comp_i, axis) ? 1 : 0;
+    d.L = c->shL[v];
+    d.U = c->shU[v];
+    d.D = c->shD[v];
+    d.modified = 0;
+  }
+  return d;
+}
+
+// Solve order of component c: modified axis first for E, x y z for H.
+void axis_order(int kindH, int sub, int c, int order[3]) {
+  if (kindH) {
+    order[0] = 0; order[1] = 1; order[2] = 2;
+    return;
+  }
+  const int m = kModAxis[sub - 1][c];
+  order[0] = m;
+  int k = 1;
+  for (int a = 0; a < 3; ++a)
+    if (a != m) order[k++] = a;
+}
+
+// Enqueue the three rounds of 1D solves of one stage on the three components
+// of `buf` (in place).  If `final_out` is given, the last solve of each
+// component writes final_out + solution instead (refine-mode correction).
+template <typename T>
+hipError_t enqueue_solves(adi_ctx* c, int kindH, int sub, void* buf, void* final_out,
+                          hipStream_t s) {
+  int order[3][3];
+  for (int ci = 0; ci < 3; ++ci) axis_order(kindH, sub, ci, order[ci]);
+  for (int r = 0; r < 3; ++r) {
+    for (int xgroup = 1; xgroup >= 0; --xgroup) {
+      SweepArgs a{};
+      int nd = 0;
+      for (int ci = 0; ci < 3; ++ci) {
+        const int ax = order[ci][r];
+        if ((ax == 0) != (xgroup == 1)) continue;
+        void* in = comp(buf, ci, c);
+        void* out = in;
+        const void* acc = nullptr;
+        if (final_out && r == 2) {
+          out = comp(final_out, ci, c);
+          acc = out;
+        }
+        a.d[nd++] = desc_for(c, kindH, sub, ci, ax, in, out, acc);
+      }
+      if (nd == 0) continue;
+      a.n = c->n;
+      a.nlines = c->n * c->n;
+      a.xaxis = xgroup;
+      a.tick_t = nullptr;
+      hipError_t e = launch_sweep<T>(c->p, nd, a, s);
+      if (e != hipSuccess) return e;
+    }
+  }
+  return hipSuccess;
+}
+
+template <typename T>
+hipError_t enqueue_step_t(adi_ctx* c, hipStream_t s) {
+  void* const* B = c->B;
+  for (int sub = 1; sub <= 2; ++sub) {
+    // buffers: substep 1: E=B0, H=B1 -> E'=B2, H'=B3; substep 2: E'=B2, H'=B3 -> E''=B0, H''=B1
+    void* Ein = sub == 1 ? B[0] : B[2];
+    void* Hin = sub == 1 ? B[1] : B[3];
+    void* Eout = sub == 1 ? B[2] : B[0];
+    void* Hout = sub == 1 ? B[3] : B[1];
+    // E stage
+    {
+      const void* f[6] = {comp(Ein, 0, c), comp(Ein, 1, c), comp(Ein, 2, c),
+                          comp(Hin, 0, c), comp(Hin, 1, c), comp(Hin, 2, c)};
+      void* out[3] = {comp(Eout, 0, c), comp(Eout, 1, c), comp(Eout, 2, c)};
+      RhsArgs<T> a = rhs_args<T>(c, f, 6, out, 0, sub);
+      hipError_t e = launch_rhs<T>(sub == 1 ? kStageE1 : kStageE2, c->p, a, s);
+      if (e != hipSuccess) return e;
+      e = enqueue_solves<T>(c, 0, sub, Eout, nullptr, s);
+      if (e != hipSuccess) return e;
+      if (c->refine()) {
+        const void* fr[9] = {f[0], f[1], f[2], f[3], f[4], f[5],
+                             comp(Eout, 0, c), comp(Eout, 1, c), comp(Eout, 2, c)};
+        void* rout[3] = {c->R32, c->R32 + c->D, c->R32 + 2 * c->D};
+        RhsArgs<double> r{};
+        for (int i = 0; i < 9; ++i) r.f[i] = fr[i];
+        for (int i = 0; i < 3; ++i) r.out[i] = rout[i];
+        r.coef[0] = c->coef64[2];
+        r.coef[1] = c->coef64[1];
+        r.coef[2] = c->coef64[0];
+        r.band = c->band64;
+        r.n = c->n;
+        r.zchunk = 32;
+        r.src = c->src;
+        r.tnow = c->d_t;
+        r.frac_dt = (sub == 1 ? 0.25 : 0.75) * c->dt;
+        e = launch_residual(sub == 1 ? kStageR1 : kStageR2, c->p, r, s);
+        if (e != hipSuccess) return e;
+        e = enqueue_solves<float>(c, 0, sub, c->R32, Eout, s);
+        if (e != hipSuccess) return e;
+      }
+    }
+    // H stage
+    {
+      const void* f[9] = {comp(Hin, 0, c),  comp(Hin, 1, c),  comp(Hin, 2, c),
+                          comp(Ein, 0, c),  comp(Ein, 1, c),  comp(Ein, 2, c),
+                          comp(Eout, 0, c), comp(Eout, 1, c), comp(Eout, 2, c)};
+      void* out[3] = {comp(Hout, 0, c), comp(Hout, 1, c), comp(Hout, 2, c)};
+      RhsArgs<T> a = rhs_args<T>(c, f, 9, out, 1, sub);
+      hipError_t e = launch_rhs<T>(sub == 1 ? kStageH1 : kStageH2, c->p, a, s);
+      if (e != hipSuccess) return e;
+      // H: x, y, z (all shared factors); the last launch advances the time
+      for (int ax = 0; ax < 3; ++ax) {
+        SweepArgs w{};
+        for (int ci = 0; ci < 3; ++ci) {
+          void* io = comp(Hout, ci, c);
+          w.d[ci] = desc_for(c, 1, sub, ci, ax, io, io, nullptr);
+        }
+        w.n = c->n;
+        w.nlines = c->n * c->n;
+        w.xaxis = ax == 0;
+        if (sub == 2 && ax == 2) {
+          w.tick_t = c->d_t;
+          w.tick_dt = c->dt;
+        }
+        e = launch_sweep<T>(c->p, 3, w, s);
+        if (e != hipSuccess) return e;
+      }
+    }
+  }
+  return hipSuccess;
+}
+
+hipError_t enqueue_step(adi_ctx* c, hipStream_t s) {
+  return c->refine() ? enqueue_step_t<float>(c, s) : enqueue_step_t<double>(c, s);
+}
+
+void drop_graph(adi_ctx* c) {
+  if (c->exec) hipGraphExecDestroy(c->exec);
+  if (c->graph) hipGraphDestroy(c->graph);
+  c->exec = nullptr;
+  c->graph = nullptr;
+}
+
+int capture(adi_ctx* c) {
+  drop_graph(c);
+  HIPCHK(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeRelaxed));
+  hipError_t e = enqueue_step(c, c->cap);
+  hipGraph_t g = nullptr;
+  hipError_t e2 = hipStreamEndCapture(c->cap, &g);
+  if (e != hipSuccess) return fail(c, ADI_EHIP, std::string("step capture: ") + hipGetErrorString(e));
+  if (e2 != hipSuccess) return fail(c, ADI_EHIP, std::string("end capture: ") + hipGetErrorString(e2));
+  c->graph = g;
+  HIPCHK(c, hipGraphInstantiate(&c->exec, g, nullptr, nullptr, 0));
+  return ADI_OK;
+}
+
+bool finite_all(const double* v, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(v[i])) return false;
+  return true;
+}
+
+int ensure_stream(adi_ctx* c) {
+  if (c->cap) return ADI_OK;
+  HIPCHK(c, hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+  return ADI_OK;
+}
+
+int ensure_workspace(adi_ctx* c) {
+  int st = ensure_stream(c);
+  if (st != ADI_OK) return st;
+  if (c->ws) return ADI_OK;
+  const size_t bytes = layout(c, nullptr);
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) return fail(c, ADI_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  c->ws = static_cast<unsigned char*>(p);
+  c->ws_bytes = bytes;
+  c->own_ws = true;
+  const size_t aligned = (reinterpret_cast<uintptr_t>(c->ws) + 255) & ~uintptr_t(255);
+  layout(c, reinterpret_cast<unsigned char*>(aligned));
+  // a defined initial state: zero fields at t = 0 (not part of any graph)
+  HIPCHK(c, hipMemset(c->B[0], 0, 6 * c->D * c->esz));
+  HIPCHK(c, hipMemset(c->d_t, 0, 8));
+  return ADI_OK;
+}
+
+}  // namespace
+
+// ====================================================================== ABI
+extern "C" {
+
+int adi_create(adi_ctx** out, int nx, int ny, int nz, int p, int precision, void* hip_stream) {
+  if (!out) return ADI_EINVAL;
+  *out = nullptr;
+  if (nx < 1 || p < 1 || p > kMaxP || nx != ny || nx != nz) return ADI_EINVAL;
+  if (precision != ADI_FP64 && precision != ADI_FP32_REFINE) return ADI_EINVAL;
+  adi_ctx* c = new adi_ctx();
+  c->N = nx;
+  c->p = p;
+  c->n = nx + p;
+  c->D = size_t(c->n) * c->n * c->n;
+  c->prec = precision;
+  c->esz = precision == ADI_FP64 ? 8 : 4;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  // the private capture stream is created on first device use, so that
+  // argument validation never touches the GPU
+  *out = c;
+  return ADI_OK;
+}
+
+int adi_ncoef(const adi_ctx* c) { return c ? c->n : ADI_EINVAL; }
+
+size_t adi_workspace_bytes(const adi_ctx* c) {
+  if (!c) return 0;
+  adi_ctx tmp;
+  tmp.N = c->N; tmp.p = c->p; tmp.n = c->n; tmp.D = c->D; tmp.prec = c->prec; tmp.esz = c->esz;
+  return layout(&tmp, nullptr);
+}
+
+int adi_bind_workspace(adi_ctx* c, void* dev_ptr, size_t bytes) {
+  if (!c || !dev_ptr) return ADI_EINVAL;
+  if (c->ws) return fail(c, ADI_ESTATE, "workspace already set");
+  const size_t need = layout(c, nullptr);
+  if (bytes < need) return fail(c, ADI_ENOMEM, "workspace too small");
+  int st = ensure_stream(c);
+  if (st != ADI_OK) return st;
+  c->ws = static_cast<unsigned char*>(dev_ptr);
+  c->ws_bytes = bytes;
+  c->own_ws = false;
+  const size_t aligned = (reinterpret_cast<uintptr_t>(c->ws) + 255) & ~uintptr_t(255);
+  layout(c, reinterpret_cast<unsigned char*>(aligned));
+  HIPCHK(c, hipMemset(c->B[0], 0, 6 * c->D * c->esz));
+  HIPCHK(c, hipMemset(c->d_t, 0, 8));
+  return ADI_OK;
+}
+
+int adi_set_material_dof(adi_ctx* c, const double* eps, const double* mu, const double* sig) {
+  if (!c || !eps || !mu || !sig) return ADI_EINVAL;
+  for (size_t i = 0; i < c->D; ++i) {
+    if (!std::isfinite(eps[i]) || !std::isfinite(mu[i]) || !std::isfinite(sig[i]))
+      return fail(c, ADI_EINVAL, "material value not finite");
+    if (!(eps[i] > 0.0) || !(mu[i] > 0.0) || sig[i] < 0.0)
+      return fail(c, ADI_EINVAL, "need eps > 0, mu > 0, sigma >= 0");
+  }
+  c->eps.assign(eps, eps + c->D);
+  c->mu.assign(mu, mu + c->D);
+  c->sig.assign(sig, sig + c->D);
+  c->have_material = true;
+  c->factored = false;
+  return ADI_OK;
+}
+
+int adi_set_material(adi_ctx* c, const double* eps_r, const double* mu_r, const double* sigma_nd,
+                     int vx, int vy, int vz, int map_mode) {
+  if (!c || !eps_r || !mu_r || !sigma_nd || vx < 1 || vy < 1 || vz < 1) return ADI_EINVAL;
+  if (map_mode != ADI_MAP_GREVILLE) return fail(c, ADI_EINVAL, "unknown material map mode");
+  const size_t V = size_t(vx) * vy * vz;
+  for (size_t i = 0; i < V; ++i) {
+    if (!std::isfinite(eps_r[i]) || !std::isfinite(mu_r[i]) || !std::isfinite(sigma_nd[i]))
+      return fail(c, ADI_EINVAL, "material value not finite");
+    if (!(eps_r[i] > 0.0) || !(mu_r[i] > 0.0) || sigma_nd[i] < 0.0)
+      return fail(c, ADI_EINVAL, "need eps > 0, mu > 0, sigma >= 0");
+  }
+  // Greville sampling: DOF (i,j,k) takes the voxel containing (xi_i, xi_j, xi_k).
+  const std::vector<double> xi = greville(c->N, c->p);
+  const int n = c->n;
+  auto vox = [](double x, int V) { return std::min(int(std::floor(x * V)), V - 1); };
+  std::vector<int> ix(n), iy(n), iz(n);
+  for (int i = 0; i < n; ++i) {
+    ix[i] = vox(xi[i], vx);
+    iy[i] = vox(xi[i], vy);
+    iz[i] = vox(xi[i], vz);
+  }
+  c->eps.resize(c->D);
+  c->mu.resize(c->D);
+  c->sig.resize(c->D);
+  for (int k = 0; k < n; ++k)
+    for (int j = 0; j < n; ++j)
+      for (int i = 0; i < n; ++i) {
+        const size_t o = i + size_t(n) * (j + size_t(n) * k);
+        const size_t v = ix[i] + size_t(vx) * (iy[j] + size_t(vy) * iz[k]);
+        c->eps[o] = eps_r[v];
+        c->mu[o] = mu_r[v];
+        c->sig[o] = sigma_nd[v];
+      }
+  c->have_material = true;
+  c->factored = false;
+  return ADI_OK;
+}
+
+int adi_set_source(adi_ctx* c, const double xs[3], int comp_i, double amp, double f0, double t0,
+                   double width) {
+  if (!c || !xs || comp_i < 0 || comp_i > 2) return ADI_EINVAL;
+  if (!(width > 0.0)) return fail(c, ADI_EINVAL, "source width must be > 0");
+  for (int a = 0; a < 3; ++a)
+    if (!(xs[a] >= 0.0 && xs[a] <= 1.0)) return fail(c, ADI_EINVAL, "source outside the domain");
+  SourceArgs s{};
+  if (amp == 0.0) {
+    s.comp = -1;
+  } else {
+    s.comp = comp_i;
+    s.amp = amp;
+    s.f0 = f0;
+    s.t0 = t0;
+    s.width = width;
+    double vals[kMaxP + 1];
+    int first;
+    basis_at(c->N, c->p, xs[0], &first, vals);
+    s.first[0] = first;
+    for (int r = 0; r <= c->p; ++r) s.bx[r] = vals[r];
+    basis_at(c->N, c->p, xs[1], &first, vals);
+    s.first[1] = first;
+    for (int r = 0; r <= c->p; ++r) s.by[r] = vals[r];
+    basis_at(c->N, c->p, xs[2], &first, vals);
+    s.first[2] = first;
+    for (int r = 0; r <= c->p; ++r) s.bz[r] = vals[r];
+  }
+  c->src = s;
+  for (int a = 0; a < 3; ++a) c->src_xs[a] = xs[a];
+  c->factored = false;
+  return ADI_OK;
+}
+
+int adi_factor(adi_ctx* c, double dt) {
+  if (!c) return ADI_EINVAL;
+  if (!c->have_material) return fail(c, ADI_ESTATE, "set the material before factor");
+  if (!std::isfinite(dt) || dt < 0.0) return fail(c, ADI_EINVAL, "dt must be finite and >= 0");
+  int st = ensure_workspace(c);
+  if (st != ADI_OK) return st;
+  const int n = c->n, p = c->p, W = 2 * p + 1;
+  const size_t D = c->D;
+  c->dt = dt;
+
+  // 1D operators (float64, exact Gauss quadrature)
+  Gram1D g = build_gram(c->N, p);
+  std::vector<double> ops(size_t(4) * n * W);
+  std::copy(g.M.begin(), g.M.end(), ops.begin());
+  std::copy(g.A.begin(), g.A.end(), ops.begin() + size_t(n) * W);
+  std::copy(g.B.begin(), g.B.end(), ops.begin() + size_t(2) * n * W);
+  std::copy(g.S.begin(), g.S.end(), ops.begin() + size_t(3) * n * W);
+  if ((st = upload(c, c->bandT, ops)) != ADI_OK) return st;
+  HIPCHK(c, hipMemcpy(c->band64, ops.data(), ops.size() * 8, hipMemcpyHostToDevice));
+
+  // shared factors of M (free) and M with Dirichlet rows/columns
+  for (int v = 0; v < 2; ++v) {
+    std::vector<double> band = g.M;
+    if (v) apply_dirichlet(band, n, p);
+    std::vector<double> L, U, Dinv;
+    const double r = band_lu(band, n, p, L, U, Dinv);
+    if (!(r > 1e-14)) return fail(c, ADI_ESINGULAR, "singular mass matrix factor");
+    if ((st = upload(c, c->shL[v], L)) != ADI_OK) return st;
+    if ((st = upload(c, c->shU[v], U)) != ADI_OK) return st;
+    if ((st = upload(c, c->shD[v], Dinv)) != ADI_OK) return st;
+  }
+
+  // per-row coefficients (material attached to test functions), with the
+  // trapezoidal conductivity term: c = sigma dt / (4 eps),
+  // alpha = dt^2/(4 eps mu (1+c)), beta = dt/(2 eps (1+c)),
+  // gamma = (1-c)/(1+c), delta = dt/(2 mu)
+  std::vector<double> co[4];
+  for (auto& v : co) v.resize(D);
+  for (size_t i = 0; i < D; ++i) {
+    const double e = c->eps[i], m = c->mu[i], s = c->sig[i];
+    const double cc = s * dt / (4.0 * e);
+    co[0][i] = dt * dt / (4.0 * e * m * (1.0 + cc));
+    co[1][i] = dt / (2.0 * e * (1.0 + cc));
+    co[2][i] = (1.0 - cc) / (1.0 + cc);
+    co[3][i] = dt / (2.0 * m);
+  }
+  for (int i = 0; i < 4; ++i) {
+    if ((st = upload(c, c->coefT[i], co[i])) != ADI_OK) return st;
+    if (c->refine())
+      HIPCHK(c, hipMemcpy(c->coef64[i], co[i].data(), D * 8, hipMemcpyHostToDevice));
+  }
+
+  // per-line factors of the modified systems (always Dirichlet: the modified
+  // axis of E_c is never axis c)
+  std::vector<double> fb(size_t(2) * n * W);
+  {
+    std::vector<double> Mb = g.M, Sb = g.S;
+    apply_dirichlet(Mb, n, p);
+    apply_dirichlet(Sb, n, p);
+    for (int b : {0, n - 1}) Sb[size_t(b) * W + p] = 0.0;  // identity rows carry no alpha S
+    std::copy(Mb.begin(), Mb.end(), fb.begin());
+    std::copy(Sb.begin(), Sb.end(), fb.begin() + size_t(n) * W);
+  }
+  HIPCHK(c, hipMemcpy(c->fb64, fb.data(), fb.size() * 8, hipMemcpyHostToDevice));
+  double worst = 1e300;
+  std::vector<double> ratios(size_t(n) * n);
+  for (int sub = 1; sub <= 2; ++sub)
+    for (int ci = 0; ci < 3; ++ci) {
+      const int s = (sub - 1) * 3 + ci;
+      FactorArgs f{};
+      f.Mb = c->fb64;
+      f.Sb = c->fb64 + size_t(n) * W;
+      f.alpha = c->coef64[0];
+      if (c->refine()) {
+        f.L32 = static_cast<float*>(c->mL[s]);
+        f.U32 = static_cast<float*>(c->mU[s]);
+        f.D32 = static_cast<float*>(c->mD[s]);
+      } else {
+        f.L64 = static_cast<double*>(c->mL[s]);
+        f.U64 = static_cast<double*>(c->mU[s]);
+        f.D64 = static_cast<double*>(c->mD[s]);
+      }
+      f.minratio = c->minratio;
+      f.n = n;
+      f.nlines = n * n;
+      f.axis = kModAxis[sub - 1][ci];
+      HIPCHK(c, launch_factor(p, f, c->cap));
+      HIPCHK(c, hipMemcpyAsync(ratios.data(), c->minratio, ratios.size() * 8,
+                               hipMemcpyDeviceToHost, c->cap));
+      HIPCHK(c, hipStreamSynchronize(c->cap));
+      for (double r : ratios) worst = std::min(worst, r);
+    }
+  if (!(worst > 1e-14)) return fail(c, ADI_ESINGULAR, "tiny pivot in a material-modified factor");
+
+  st = capture(c);
+  if (st != ADI_OK) return st;
+  c->factored = true;
+  return ADI_OK;
+}
+
+int adi_set_fields(adi_ctx* c, const double* EH, double t) {
+  if (!c || !EH) return ADI_EINVAL;
+  if (!finite_all(EH, 6 * c->D) || !std::isfinite(t))
+    return fail(c, ADI_ENONFINITE, "field value not finite");
+  if (!c->ws) {
+    int st = ensure_workspace(c);
+    if (st != ADI_OK) return st;
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (c->esz == 8) {
+    HIPCHK(c, hipMemcpy(c->B[0], EH, 6 * c->D * 8, hipMemcpyHostToDevice));
+  } else {
+    std::vector<float> f(EH, EH + 6 * c->D);
+    HIPCHK(c, hipMemcpy(c->B[0], f.data(), f.size() * 4, hipMemcpyHostToDevice));
+  }
+  HIPCHK(c, hipMemcpy(c->d_t, &t, 8, hipMemcpyHostToDevice));
+  c->t = t;
+  return ADI_OK;
+}
+
+int adi_step(adi_ctx* c, int nsteps) {
+  if (!c || nsteps < 0) return ADI_EINVAL;
+  if (!c->factored || !c->exec) return fail(c, ADI_ESTATE, "adi_factor must succeed before adi_step");
+  for (int i = 0; i < nsteps; ++i) HIPCHK(c, hipGraphLaunch(c->exec, c->stream));
+  c->t += nsteps * c->dt;
+  return ADI_OK;
+}
+
+int adi_get_fields(adi_ctx* c, double* EH_out, double* t_out) {
+  if (!c || !EH_out) return ADI_EINVAL;
+  if (!c->ws) return fail(c, ADI_ESTATE, "no state");
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (c->esz == 8) {
+    HIPCHK(c, hipMemcpy(EH_out, c->B[0], 6 * c->D * 8, hipMemcpyDeviceToHost));
+  } else {
+    std::vector<float> f(6 * c->D);
+    HIPCHK(c, hipMemcpy(f.data(), c->B[0], f.size() * 4, hipMemcpyDeviceToHost));
+    for (size_t i = 0; i < f.size(); ++i) EH_out[i] = f[i];
+  }
+  double t = 0.0;
+  HIPCHK(c, hipMemcpy(&t, c->d_t, 8, hipMemcpyDeviceToHost));
+  if (t_out) *t_out = t;
+  return ADI_OK;
+}
+
+int adi_fields_device(adi_ctx* c, void** dev, int* dtype) {
+  if (!c || !dev || !dtype) return ADI_EINVAL;
+  if (!c->ws) return fail(c, ADI_ESTATE, "no state");
+  *dev = c->B[0];
+  *dtype = c->esz == 8 ? 0 : 1;
+  return ADI_OK;
+}
+
+int adi_sync(adi_ctx* c) {
+  if (!c) return ADI_EINVAL;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return ADI_OK;
+}
+
+const char* adi_last_error(const adi_ctx* c) { return c ? c->err.c_str() : "invalid handle"; }
+
+void adi_destroy(adi_ctx* c) {
+  if (!c) return;
+  if (c->stream) hipStreamSynchronize(c->stream);
+  drop_graph(c);
+  if (c->own_ws && c->ws) hipFree(c->ws);
+  if (c->cap) hipStreamDestroy(c->cap);
+  delete c;
+}
+
+// ------------------------------------------------------------- test hooks
+int adi_rhs(adi_ctx* c, int stage, int sub, const double* in, double t, double* out) {
+  if (!c || !in || !out || (stage != 0 && stage != 1) || (sub != 1 && sub != 2)) return ADI_EINVAL;
+  if (!c->factored) return fail(c, ADI_ESTATE, "adi_factor first");
+  const int nf = stage == 0 ? 6 : 9;
+  const size_t D = c->D, es = c->esz;
+  void* din = nullptr;
+  void* dout = nullptr;
+  HIPCHK(c, hipMalloc(&din, nf * D * es));
+  HIPCHK(c, hipMalloc(&dout, 3 * D * es));
+  int st = ADI_OK;
+  do {
+    std::vector<double> v(in, in + nf * D);
+    if ((st = upload(c, din, v)) != ADI_OK) break;
+    double tt = t;
+    if (hipMemcpy(c->d_t, &tt, 8, hipMemcpyHostToDevice) != hipSuccess) { st = fail(c, ADI_EHIP, "copy t"); break; }
+    const void* f[9];
+    for (int i = 0; i < nf; ++i) f[i] = static_cast<unsigned char*>(din) + size_t(i) * D * es;
+    void* o[3] = {dout, static_cast<unsigned char*>(dout) + D * es,
+                  static_cast<unsigned char*>(dout) + 2 * D * es};
+    const int kind = stage == 0 ? (sub == 1 ? kStageE1 : kStageE2) : (sub == 1 ? kStageH1 : kStageH2);
+    hipError_t e;
+    if (es == 8) e = launch_rhs<double>(kind, c->p, rhs_args<double>(c, f, nf, o, stage, sub), c->cap);
+    else e = launch_rhs<float>(kind, c->p, rhs_args<float>(c, f, nf, o, stage, sub), c->cap);
+    if (e != hipSuccess || hipStreamSynchronize(c->cap) != hipSuccess) { st = fail(c, ADI_EHIP, "rhs kernel"); break; }
+    if (es == 8) {
+      if (hipMemcpy(out, dout, 3 * D * 8, hipMemcpyDeviceToHost) != hipSuccess) { st = fail(c, ADI_EHIP, "copy"); break; }
+    } else {
+      std::vector<float> f32(3 * D);
+      if (hipMemcpy(f32.data(), dout, 3 * D * 4, hipMemcpyDeviceToHost) != hipSuccess) { st = fail(c, ADI_EHIP, "copy"); break; }
+      for (size_t i = 0; i < f32.size(); ++i) out[i] = f32[i];
+    }
+    double t0 = c->t;
+    hipMemcpy(c->d_t, &t0, 8, hipMemcpyHostToDevice);
+  } while (false);
+  hipFree(din);
+  hipFree(dout);
+  return st;
+}
+
+int adi_solve(adi_ctx* c, int stage, int sub, double* inout) {
+  if (!c || !inout || (stage != 0 && stage != 1) || (sub != 1 && sub != 2)) return ADI_EINVAL;
+  if (!c->factored) return fail(c, ADI_ESTATE, "adi_factor first");
+  const size_t D = c->D, es = c->esz;
+  void* d = nullptr;
+  HIPCHK(c, hipMalloc(&d, 3 * D * es));
+  int st = ADI_OK;
+  do {
+    std::vector<double> v(inout, inout + 3 * D);
+    if ((st = upload(c, d, v)) != ADI_OK) break;
+    hipError_t e = es == 8 ? enqueue_solves<double>(c, stage, sub, d, nullptr, c->cap)
+                           : enqueue_solves<float>(c, stage, sub, d, nullptr, c->cap);
+    if (e != hipSuccess || hipStreamSynchronize(c->cap) != hipSuccess) { st = fail(c, ADI_EHIP, "solve kernels"); break; }
+    if (es == 8) {
+      if (hipMemcpy(inout, d, 3 * D * 8, hipMemcpyDeviceToHost) != hipSuccess) { st = fail(c, ADI_EHIP, "copy"); break; }
+    } else {
+      std::vector<float> f32(3 * D);
+      if (hipMemcpy(f32.data(), d, 3 * D * 4, hipMemcpyDeviceToHost) != hipSuccess) { st = fail(c, ADI_EHIP, "copy"); break; }
+      for (size_t i = 0; i < f32.size(); ++i) inout[i] = f32[i];
+    }
+  } while (false);
+  hipFree(d);
+  return st;
+}
+
+}  // extern "C"

@@ -1,0 +1,105 @@
+// Internal declarations shared by the host driver and the HIP kernels of
+// libadimx.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+namespace adimx {
+
+constexpr int kMaxP = 4;  // largest supported B-spline degree
+
+// ---------------------------------------------------------------- host (FP64)
+struct Gram1D {
+  int N = 0, p = 0, n = 0;
+  std::vector<double> M, S, A, B;  // bands, n x (2p+1): band[r*(2p+1)+d] = X[r][r+d-p]
+};
+
+std::vector<double> open_knots(int N, int p);
+int find_span(const std::vector<double>& t, int p, int n, double x);
+void basis_on_span(const std::vector<double>& t, int p, int span, double x, double* val,
+                   double* der);
+void gauss_legendre(int q, std::vector<double>& x, std::vector<double>& w);
+Gram1D build_gram(int N, int p);
+void apply_dirichlet(std::vector<double>& band, int n, int p);
+double band_lu(const std::vector<double>& band, int n, int p, std::vector<double>& L,
+               std::vector<double>& Uoff, std::vector<double>& Uinv);
+std::vector<double> greville(int N, int p);
+void basis_at(int N, int p, double x, int* first, double* vals);
+
+// ---------------------------------------------------------------- kernels
+// Stage kinds of the right-hand-side kernel.
+enum RhsStage : int {
+  kStageE1 = 0,   // E right-hand sides, substep 1 (eq. discrete1)
+  kStageE2 = 1,   // E right-hand sides, substep 2 (eq. discrete3)
+  kStageH1 = 2,   // H right-hand sides, substep 1 (eq. discrete2)
+  kStageH2 = 3,   // H right-hand sides, substep 2 (eq. discrete4)
+  kStageR1 = 4,   // E residual b - P x of substep 1 (float64 correction)
+  kStageR2 = 5,   // E residual of substep 2
+};
+
+struct SourceArgs {
+  int comp = -1;                   // field component carrying the dipole, -1: none
+  int first[3] = {0, 0, 0};        // first nonzero basis index per axis
+  double bx[kMaxP + 1] = {0}, by[kMaxP + 1] = {0}, bz[kMaxP + 1] = {0};
+  double amp = 0, f0 = 0, t0 = 0, width = 1;
+};
+
+template <typename T>
+struct RhsArgs {
+  const void* f[9];       // input fields (E stage: E1..E3,H1..H3; H stage: H1..H3,
+                          // E_old1..3, E_new1..3; residual: E1..E3,H1..H3,X1..X3)
+  void* out[3];           // T (or float for the residual in refine mode)
+  const T* coef[3];       // E: gamma, beta, alpha ; H: delta
+  const T* band;          // [op][r][2p+1], op 0 = M, 1 = A, 2 = B, 3 = S
+  int n;
+  int zchunk;
+  SourceArgs src;
+  const double* tnow;     // device time at the start of the step
+  double frac_dt;         // (1/4 or 3/4) * dt
+};
+
+struct SweepDesc {
+  int axis;               // 0 = x, 1 = y, 2 = z
+  void* in;               // right-hand sides (T)
+  void* out;              // solution (T); may equal in
+  const void* acc;        // if non-null, out = solution + acc (element-wise)
+  const void* L;          // factors; shared: [r*P + k-1], modified: [((k-1)*n + r)*nlines + l]
+  const void* U;
+  const void* D;          // inverse diagonal; shared: [r], modified: [r*nlines + l]
+  int modified;           // 0 = shared factors, 1 = per-line factors
+};
+
+struct SweepArgs {
+  SweepDesc d[3];         // blockIdx.y selects the descriptor
+  int n;
+  int nlines;
+  int xaxis;              // 1: all descriptors are x lines (transposing kernel)
+  double* tick_t;         // if non-null, block (0,0) thread 0 does *tick_t += tick_dt
+  double tick_dt;
+};
+
+struct FactorArgs {
+  const double* Mb;       // band of the base matrix (Dirichlet rows applied)
+  const double* Sb;       // band of the stiffness matrix (Dirichlet rows/cols zero)
+  const double* alpha;    // per-DOF coefficient (n^3, x fastest)
+  double* L64; double* U64; double* D64;   // per-line factors (float64)
+  float* L32; float* U32; float* D32;      // float32 copies (refine mode) or null
+  double* minratio;       // per line: min |U_rr| / |A_rr|
+  int n, nlines, axis;
+};
+
+// Launchers (kernels.hip).  All enqueue on `stream` and return hipError_t.
+template <typename T>
+hipError_t launch_rhs(int stage, int p, const RhsArgs<T>& a, hipStream_t stream);
+hipError_t launch_residual(int stage, int p, const RhsArgs<double>& a, hipStream_t stream);
+template <typename T>
+hipError_t launch_sweep(int p, int ndesc, const SweepArgs& a, hipStream_t stream);
+hipError_t launch_factor(int p, const FactorArgs& a, hipStream_t stream);
+template <typename T>
+hipError_t launch_convert(const void* src, void* dst, size_t count, int dir, hipStream_t stream);
+
+}  // namespace adimx

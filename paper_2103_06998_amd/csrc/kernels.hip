@@ -1,0 +1,597 @@
+// gfx950 kernels of the ADI step: right-hand-side assembly, banded line
+// sweeps and the per-line float64 factorisation of material-modified rows.
+//
+// Data layout: every field component is an n^3 array, x fastest ([z][y][x]),
+// the paper's reordering of a right-hand side into N_x-long rows.
+#include "adimx_internal.h"
+
+#include <type_traits>
+#include <utility>
+
+namespace adimx {
+
+namespace {
+
+// ------------------------------------------------------------ term tables
+// One sum-factorised term of a right-hand side: output component `out`,
+// coefficient group `grp`, sign, input field, and the 1D operators acting on
+// x, y and z (0 = M mass, 1 = A trial derivative, 2 = B = A^T test
+// derivative, 3 = S stiffness).  Each output value is
+//   sum_g coef_g[row] * sum_{terms in g} sign * (X (x) Y (x) Z) field.
+struct Term {
+  int out, grp, sign, field, x, y, z;
+};
+constexpr int OM = 0, OA = 1, OB = 2, OS = 3;
+
+// Stage kinds and their tables.
+//  E stages (fields E1,E2,E3,H1,H2,H3; groups gamma, beta, alpha):
+//    discrete1 / dupa1ab: RE1 = g MMM E1 + b (MAM H3 - MMA H2) + a ABM E2, ...
+//    discrete3:           alpha terms AMB E3, BAM E1, MBA E2.
+//  H stages (fields H1..3, E_old1..3, E_new1..3; groups 1, delta):
+//    discrete2: RH1 = MMM H1 - d MAM E3 + d MMA E2', ...
+//    discrete4: RH1 = MMM H1 + d MMA E2' - d MAM E3'', ... (sign of scheme1d)
+//  Residual stages (fields E, H, X = float32 solution; groups gamma, beta,
+//    alpha, 1): the E right-hand side minus (M..M) X minus alpha (..S..) X.
+template <int STAGE>
+struct StageInfo;
+template <> struct StageInfo<kStageE1> { static constexpr int NT = 12, NF = 6, NG = 3; };
+template <> struct StageInfo<kStageE2> { static constexpr int NT = 12, NF = 6, NG = 3; };
+template <> struct StageInfo<kStageH1> { static constexpr int NT = 9, NF = 9, NG = 2; };
+template <> struct StageInfo<kStageH2> { static constexpr int NT = 9, NF = 9, NG = 2; };
+template <> struct StageInfo<kStageR1> { static constexpr int NT = 18, NF = 9, NG = 4; };
+template <> struct StageInfo<kStageR2> { static constexpr int NT = 18, NF = 9, NG = 4; };
+
+template <int STAGE>
+__host__ __device__ constexpr Term get_term(int i) {
+  constexpr Term curl_and_mass[9] = {
+      {0, 0, +1, 0, OM, OM, OM}, {0, 1, +1, 5, OM, OA, OM}, {0, 1, -1, 4, OM, OM, OA},
+      {1, 0, +1, 1, OM, OM, OM}, {1, 1, +1, 3, OM, OM, OA}, {1, 1, -1, 5, OA, OM, OM},
+      {2, 0, +1, 2, OM, OM, OM}, {2, 1, +1, 4, OA, OM, OM}, {2, 1, -1, 3, OM, OA, OM}};
+  constexpr Term r_sub1[3] = {{0, 2, +1, 1, OA, OB, OM}, {1, 2, +1, 2, OM, OA, OB},
+                              {2, 2, +1, 0, OB, OM, OA}};
+  constexpr Term r_sub2[3] = {{0, 2, +1, 2, OA, OM, OB}, {1, 2, +1, 0, OB, OA, OM},
+                              {2, 2, +1, 1, OM, OB, OA}};
+  // minus the product operator applied to X: mass part and the stiffness
+  // part on the modified axis (substep 1: E1 y, E2 z, E3 x; substep 2: E1 z,
+  // E2 x, E3 y)
+  constexpr Term px_sub1[6] = {{0, 3, -1, 6, OM, OM, OM}, {0, 2, -1, 6, OM, OS, OM},
+                               {1, 3, -1, 7, OM, OM, OM}, {1, 2, -1, 7, OM, OM, OS},
+                               {2, 3, -1, 8, OM, OM, OM}, {2, 2, -1, 8, OS, OM, OM}};
+  constexpr Term px_sub2[6] = {{0, 3, -1, 6, OM, OM, OM}, {0, 2, -1, 6, OM, OM, OS},
+                               {1, 3, -1, 7, OM, OM, OM}, {1, 2, -1, 7, OS, OM, OM},
+                               {2, 3, -1, 8, OM, OM, OM}, {2, 2, -1, 8, OM, OS, OM}};
+  constexpr Term h_sub1[9] = {
+      {0, 0, +1, 0, OM, OM, OM}, {0, 1, -1, 5, OM, OA, OM}, {0, 1, +1, 7, OM, OM, OA},
+      {1, 0, +1, 1, OM, OM, OM}, {1, 1, -1, 3, OM, OM, OA}, {1, 1, +1, 8, OA, OM, OM},
+      {2, 0, +1, 2, OM, OM, OM}, {2, 1, -1, 4, OA, OM, OM}, {2, 1, +1, 6, OM, OA, OM}};
+  constexpr Term h_sub2[9] = {
+      {0, 0, +1, 0, OM, OM, OM}, {0, 1, +1, 4, OM, OM, OA}, {0, 1, -1, 8, OM, OA, OM},
+      {1, 0, +1, 1, OM, OM, OM}, {1, 1, +1, 5, OA, OM, OM}, {1, 1, -1, 6, OM, OM, OA},
+      {2, 0, +1, 2, OM, OM, OM}, {2, 1, +1, 3, OM, OA, OM}, {2, 1, -1, 7, OA, OM, OM}};
+  if (STAGE == kStageH1) return h_sub1[i];
+  if (STAGE == kStageH2) return h_sub2[i];
+  if (i < 9) return curl_and_mass[i];
+  const bool sub2 = (STAGE == kStageE2 || STAGE == kStageR2);
+  if (i < 12) return sub2 ? r_sub2[i - 9] : r_sub1[i - 9];
+  return sub2 ? px_sub2[i - 12] : px_sub1[i - 12];
+}
+
+// Distinct (field, y-operator) pairs: each is applied once per plane.
+struct PairTab {
+  int np = 0;
+  int field[24] = {};
+  int yop[24] = {};
+  int of_term[24] = {};
+};
+
+template <int STAGE>
+constexpr PairTab make_pairs() {
+  PairTab t{};
+  for (int i = 0; i < StageInfo<STAGE>::NT; ++i) {
+    const Term tm = get_term<STAGE>(i);
+    int found = -1;
+    for (int k = 0; k < t.np; ++k)
+      if (t.field[k] == tm.field && t.yop[k] == tm.y) found = k;
+    if (found < 0) {
+      found = t.np++;
+      t.field[found] = tm.field;
+      t.yop[found] = tm.y;
+    }
+    t.of_term[i] = found;
+  }
+  return t;
+}
+
+template <int N, typename F, int... I>
+__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  static_for_impl<N>(f, std::make_integer_sequence<int, N>{});
+}
+
+constexpr int kTX = 32, kTY = 8, kRhsThreads = kTX * kTY;
+
+template <typename TC, int P, int STAGE>
+constexpr size_t rhs_lds_bytes() {
+  constexpr int W = 2 * P + 1, HX = kTX + 2 * P, HY = kTY + 2 * P;
+  constexpr PairTab PT = make_pairs<STAGE>();
+  return sizeof(TC) * (size_t(StageInfo<STAGE>::NF) * HY * HX + size_t(PT.np) * kTY * HX +
+                       4 * kTX * W + 4 * kTY * W);
+}
+
+// ------------------------------------------------------------ RHS kernel
+// Block = a kTX x kTY tile of (x, y) output columns and a chunk of z planes.
+// Input planes are marched along z: each plane of every input field is
+// staged (with a p-halo in x and y) in LDS, the y operators then the x
+// operators are applied in the plane, and the result is scattered into a
+// register queue of 2p+1 pending output planes with the z operator's
+// weights.  When the oldest pending plane is complete it is scaled by the
+// per-row coefficients and written.  TI: input type, TC: arithmetic type,
+// TO: output type.
+template <typename TI, typename TC, typename TO, int P, int STAGE>
+__global__ __launch_bounds__(kRhsThreads) void rhs_kernel(RhsArgs<TC> a) {
+  constexpr int W = 2 * P + 1, HX = kTX + 2 * P, HY = kTY + 2 * P;
+  constexpr int NT = StageInfo<STAGE>::NT, NF = StageInfo<STAGE>::NF, NG = StageInfo<STAGE>::NG;
+  constexpr PairTab PT = make_pairs<STAGE>();
+  constexpr int NP = PT.np;
+  constexpr bool kE = !(STAGE == kStageH1 || STAGE == kStageH2);
+
+  extern __shared__ __align__(16) unsigned char smem[];
+  TC* sF = reinterpret_cast<TC*>(smem);
+  TC* sG = sF + NF * HY * HX;
+  TC* sBX = sG + NP * kTY * HX;
+  TC* sBY = sBX + 4 * kTX * W;
+
+  const int n = a.n;
+  const size_t plane = size_t(n) * n;
+  const int tid = threadIdx.x, tx = tid % kTX, ty = tid / kTX;
+  const int i0 = blockIdx.x * kTX, j0 = blockIdx.y * kTY;
+  const int t0 = blockIdx.z * a.zchunk;
+  const int t1 = min(n, t0 + a.zchunk);
+  const TC* band = a.band;
+
+  for (int idx = tid; idx < 4 * kTX * W; idx += kRhsThreads) {
+    const int op = idx / (kTX * W), rem = idx % (kTX * W), r = rem / W, d = rem % W;
+    const int gi = i0 + r;
+    sBX[idx] = gi < n ? band[(size_t(op) * n + gi) * W + d] : TC(0);
+  }
+  for (int idx = tid; idx < 4 * kTY * W; idx += kRhsThreads) {
+    const int op = idx / (kTY * W), rem = idx % (kTY * W), r = rem / W, d = rem % W;
+    const int gj = j0 + r;
+    sBY[idx] = gj < n ? band[(size_t(op) * n + gj) * W + d] : TC(0);
+  }
+
+  TC acc[3 * NG][W];
+#pragma unroll
+  for (int g = 0; g < 3 * NG; ++g)
+#pragma unroll
+    for (int q = 0; q < W; ++q) acc[g][q] = TC(0);
+
+  // source value at the midpoint of the substep (uniform)
+  double jsrc = 0.0;
+  if (kE && a.src.comp >= 0) {
+    const double tm = *a.tnow + a.frac_dt;
+    const double s = tm - a.src.t0;
+    jsrc = a.src.amp * sin(2.0 * 3.14159265358979323846 * a.src.f0 * s) *
+           exp(-(s / a.src.width) * (s / a.src.width));
+  }
+
+  for (int k = t0 - P; k < t1 + P; ++k) {
+    if (k >= 0 && k < n) {
+      __syncthreads();
+      for (int idx = tid; idx < NF * HY * HX; idx += kRhsThreads) {
+        const int f = idx / (HY * HX), rem = idx % (HY * HX), yy = rem / HX, xx = rem % HX;
+        const int gi = i0 - P + xx, gj = j0 - P + yy;
+        TC v = TC(0);
+        if (gi >= 0 && gi < n && gj >= 0 && gj < n)
+          v = TC(static_cast<const TI*>(a.f[f])[gi + size_t(n) * gj + plane * k]);
+        sF[idx] = v;
+      }
+      __syncthreads();
+      static_for<NP>([&](auto pc) {
+        constexpr int pr = decltype(pc)::value;
+        constexpr int f = PT.field[pr], yop = PT.yop[pr];
+        for (int idx = tid; idx < kTY * HX; idx += kRhsThreads) {
+          const int yy = idx / HX, xx = idx % HX;
+          TC s = TC(0);
+#pragma unroll
+          for (int d = 0; d < W; ++d) s += sBY[(yop * kTY + yy) * W + d] * sF[(f * HY + yy + d) * HX + xx];
+          sG[(pr * kTY + yy) * HX + xx] = s;
+        }
+      });
+      __syncthreads();
+      static_for<NT>([&](auto ic) {
+        constexpr int it = decltype(ic)::value;
+        constexpr Term tm = get_term<STAGE>(it);
+        constexpr int pr = PT.of_term[it];
+        TC v = TC(0);
+#pragma unroll
+        for (int d = 0; d < W; ++d) v += sBX[(tm.x * kTX + tx) * W + d] * sG[(pr * kTY + ty) * HX + tx + d];
+        if (tm.sign < 0) v = -v;
+#pragma unroll
+        for (int q = 0; q < W; ++q) {
+          const int t = k - P + q;
+          if (t >= 0 && t < n) acc[tm.out * NG + tm.grp][q] += band[(size_t(tm.z) * n + t) * W + (k - t + P)] * v;
+        }
+      });
+    }
+    const int te = k - P;
+    if (te >= t0 && te < t1) {
+      const int i = i0 + tx, j = j0 + ty;
+      if (i < n && j < n) {
+        const size_t o = i + size_t(n) * j + plane * te;
+        const bool bi = (i == 0 || i == n - 1), bj = (j == 0 || j == n - 1),
+                   bk = (te == 0 || te == n - 1);
+        if (kE) {
+          const TC g = a.coef[0][o], b = a.coef[1][o], al = a.coef[2][o];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            TC v = g * acc[c * NG + 0][0] + b * acc[c * NG + 1][0] + al * acc[c * NG + 2][0];
+            if (NG == 4) v += acc[c * NG + (NG - 1)][0];
+            if (c == a.src.comp) {
+              const int ri = i - a.src.first[0], rj = j - a.src.first[1], rk = te - a.src.first[2];
+              if (ri >= 0 && ri <= P && rj >= 0 && rj <= P && rk >= 0 && rk <= P)
+                v -= b * TC(jsrc * (a.src.bz[rk] * a.src.by[rj] * a.src.bx[ri]));
+            }
+            // E_c is constrained on the faces normal to the two other axes
+            const bool bnd = (c == 0) ? (bj || bk) : (c == 1) ? (bi || bk) : (bi || bj);
+            static_cast<TO*>(a.out[c])[o] = bnd ? TO(0) : TO(v);
+          }
+        } else {
+          const TC dl = a.coef[0][o];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const TC v = acc[c * NG + 0][0] + dl * acc[c * NG + 1][0];
+            // H_c is constrained on the faces normal to axis c
+            const bool bnd = (c == 0) ? bi : (c == 1) ? bj : bk;
+            static_cast<TO*>(a.out[c])[o] = bnd ? TO(0) : TO(v);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < 3 * NG; ++g) {
+#pragma unroll
+      for (int q = 0; q < W - 1; ++q) acc[g][q] = acc[g][q + 1];
+      acc[g][W - 1] = TC(0);
+    }
+  }
+}
+
+// ------------------------------------------------------------ sweeps
+// One wave (64 lanes) solves 64 lines: lane = line.  The 64 x n tile is
+// staged through LDS (row pitch 65 elements: conflict-free column access and
+// transposed stores for x lines), the forward and backward substitutions run
+// in LDS, and the tile is written back.  Lines along y and z are loaded with
+// consecutive lanes on consecutive x (coalesced); lines along x are contiguous
+// in memory and are transposed through LDS.
+constexpr int kPitch = 65;
+
+template <typename T, int P, bool XAX>
+__global__ __launch_bounds__(64) void sweep_kernel(SweepArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* buf = reinterpret_cast<T*>(smem);
+  const SweepDesc& ds = a.d[blockIdx.y];
+  const int n = a.n, nl = a.nlines, lane = threadIdx.x;
+  const int l0 = blockIdx.x * 64, l = l0 + lane;
+  const bool act = l < nl;
+  const T* in = static_cast<const T*>(ds.in);
+  T* out = static_cast<T*>(ds.out);
+  const T* accp = static_cast<const T*>(ds.acc);
+  const size_t n2 = size_t(n) * n;
+  const size_t lbase = (ds.axis == 1) ? size_t(l % n) + size_t(l / n) * n2 : size_t(l);
+  const size_t rstride = (ds.axis == 1) ? size_t(n) : n2;
+
+  if (XAX) {
+    for (int ll = 0; ll < 64; ++ll) {
+      const int L = l0 + ll;
+      if (L >= nl) break;
+      const T* src = in + size_t(L) * n;
+      for (int r = lane; r < n; r += 64) buf[r * kPitch + ll] = src[r];
+    }
+  } else {
+    for (int r = 0; r < n; ++r) buf[r * kPitch + lane] = act ? in[lbase + size_t(r) * rstride] : T(0);
+  }
+  __syncthreads();
+
+  if (act) {
+    const size_t fstride = size_t(n) * nl;
+    T h[P];
+#pragma unroll
+    for (int k = 0; k < P; ++k) h[k] = T(0);
+    if (!ds.modified) {
+      const T* Ls = static_cast<const T*>(ds.L);
+      for (int r = 0; r < n; ++r) {
+        T s = buf[r * kPitch + lane];
+#pragma unroll
+        for (int k = 0; k < P; ++k) s -= Ls[r * P + k] * h[k];
+#pragma unroll
+        for (int k = P - 1; k > 0; --k) h[k] = h[k - 1];
+        h[0] = s;
+        buf[r * kPitch + lane] = s;
+      }
+    } else {
+      const T* Lm = static_cast<const T*>(ds.L);
+      for (int r = 0; r < n; ++r) {
+        T s = buf[r * kPitch + lane];
+#pragma unroll
+        for (int k = 0; k < P; ++k) s -= Lm[k * fstride + size_t(r) * nl + l] * h[k];
+#pragma unroll
+        for (int k = P - 1; k > 0; --k) h[k] = h[k - 1];
+        h[0] = s;
+        buf[r * kPitch + lane] = s;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < P; ++k) h[k] = T(0);
+    if (!ds.modified) {
+      const T* Us = static_cast<const T*>(ds.U);
+      const T* Dd = static_cast<const T*>(ds.D);
+      for (int r = n - 1; r >= 0; --r) {
+        T s = buf[r * kPitch + lane];
+#pragma unroll
+        for (int k = 0; k < P; ++k) s -= Us[r * P + k] * h[k];
+        s *= Dd[r];
+#pragma unroll
+        for (int k = P - 1; k > 0; --k) h[k] = h[k - 1];
+        h[0] = s;
+        buf[r * kPitch + lane] = s;
+      }
+    } else {
+      const T* Um = static_cast<const T*>(ds.U);
+      const T* Dm = static_cast<const T*>(ds.D);
+      for (int r = n - 1; r >= 0; --r) {
+        T s = buf[r * kPitch + lane];
+#pragma unroll
+        for (int k = 0; k < P; ++k) s -= Um[k * fstride + size_t(r) * nl + l] * h[k];
+        s *= Dm[size_t(r) * nl + l];
+#pragma unroll
+        for (int k = P - 1; k > 0; --k) h[k] = h[k - 1];
+        h[0] = s;
+        buf[r * kPitch + lane] = s;
+      }
+    }
+  }
+  __syncthreads();
+
+  if (XAX) {
+    for (int ll = 0; ll < 64; ++ll) {
+      const int L = l0 + ll;
+      if (L >= nl) break;
+      const size_t base = size_t(L) * n;
+      for (int r = lane; r < n; r += 64) {
+        T v = buf[r * kPitch + ll];
+        if (accp) v += accp[base + r];
+        out[base + r] = v;
+      }
+    }
+  } else if (act) {
+    for (int r = 0; r < n; ++r) {
+      const size_t o = lbase + size_t(r) * rstride;
+      T v = buf[r * kPitch + lane];
+      if (accp) v += accp[o];
+      out[o] = v;
+    }
+  }
+  if (a.tick_t && blockIdx.x == 0 && blockIdx.y == 0 && lane == 0) *a.tick_t += a.tick_dt;
+}
+
+// ------------------------------------------------------------ factorisation
+// Pivot-free banded Doolittle LU of the material-modified 1D matrices, one
+// line per thread, in float64.  Row r of line l is Mb[r,:] + alpha[pos] Sb[r,:]
+// with alpha read at the row's own position (the row's test function), so
+// the factors are those of the row-scaled 1D system of eq. dupa1abcdefg.
+template <int P>
+__global__ __launch_bounds__(64) void factor_kernel(FactorArgs a) {
+  constexpr int W = 2 * P + 1;
+  const int l = blockIdx.x * 64 + threadIdx.x;
+  if (l >= a.nlines) return;
+  const int n = a.n, nl = a.nlines;
+  const size_t n2 = size_t(n) * n;
+  size_t lbase, rstride;
+  if (a.axis == 0) { lbase = size_t(l) * n; rstride = 1; }
+  else if (a.axis == 1) { lbase = size_t(l % n) + size_t(l / n) * n2; rstride = n; }
+  else { lbase = l; rstride = n2; }
+  const size_t fstride = size_t(n) * nl;
+
+  double up[P + 1][P + 1];  // up[m][c] = U_{i-m, i-m+c}
+#pragma unroll
+  for (int m = 0; m <= P; ++m)
+#pragma unroll
+    for (int c = 0; c <= P; ++c) up[m][c] = 0.0;
+  double minr = 1e300;
+  for (int i = 0; i < n; ++i) {
+    const double al = a.alpha[lbase + size_t(i) * rstride];
+    double A[W];
+#pragma unroll
+    for (int d = 0; d < W; ++d) A[d] = a.Mb[size_t(i) * W + d] + al * a.Sb[size_t(i) * W + d];
+    double Lr[P + 1];
+    Lr[0] = 1.0;
+#pragma unroll
+    for (int m = P; m >= 1; --m) {
+      if (i - m < 0) {
+        Lr[m] = 0.0;
+        continue;
+      }
+      double s = A[P - m];
+#pragma unroll
+      for (int mp = m + 1; mp <= P; ++mp) s -= Lr[mp] * up[mp][mp - m];
+      Lr[m] = s / up[m][0];
+    }
+    double ur[P + 1];
+#pragma unroll
+    for (int c = 0; c <= P; ++c) {
+      double s = A[P + c];
+#pragma unroll
+      for (int mp = 1; mp <= P - c; ++mp) s -= Lr[mp] * up[mp][c + mp];
+      ur[c] = s;
+    }
+    const double dinv = 1.0 / ur[0];
+#pragma unroll
+    for (int m = 1; m <= P; ++m) {
+      const size_t o = size_t(m - 1) * fstride + size_t(i) * nl + l;
+      if (a.L64) {
+        a.L64[o] = Lr[m];
+        a.U64[o] = ur[m];
+      }
+      if (a.L32) {
+        a.L32[o] = float(Lr[m]);
+        a.U32[o] = float(ur[m]);
+      }
+    }
+    if (a.D64) a.D64[size_t(i) * nl + l] = dinv;
+    if (a.D32) a.D32[size_t(i) * nl + l] = float(dinv);
+    const double ratio = fabs(ur[0]) / fabs(A[P]);
+    minr = ratio < minr ? ratio : minr;
+#pragma unroll
+    for (int m = P; m >= 2; --m)
+#pragma unroll
+      for (int c = 0; c <= P; ++c) up[m][c] = up[m - 1][c];
+#pragma unroll
+    for (int c = 0; c <= P; ++c) up[1][c] = ur[c];
+  }
+  a.minratio[l] = minr;
+}
+
+template <typename S, typename D>
+__global__ void convert_kernel(const S* __restrict__ src, D* __restrict__ dst, size_t count) {
+  const size_t stride = size_t(gridDim.x) * blockDim.x;
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < count; i += stride)
+    dst[i] = D(src[i]);
+}
+
+template <typename K>
+hipError_t set_lds(K kernel, size_t bytes) {
+  if (bytes <= 65536) return hipSuccess;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
+}
+
+template <typename TI, typename TC, typename TO, int P, int STAGE>
+hipError_t launch_rhs_t(const RhsArgs<TC>& a, hipStream_t s) {
+  auto k = rhs_kernel<TI, TC, TO, P, STAGE>;
+  const size_t lds = rhs_lds_bytes<TC, P, STAGE>();
+  hipError_t e = set_lds(k, lds);
+  if (e != hipSuccess) return e;
+  const int n = a.n;
+  dim3 grid((n + kTX - 1) / kTX, (n + kTY - 1) / kTY, (n + a.zchunk - 1) / a.zchunk);
+  hipLaunchKernelGGL(k, grid, dim3(kRhsThreads), lds, s, a);
+  return hipGetLastError();
+}
+
+template <typename TI, typename TC, typename TO, int P>
+hipError_t launch_rhs_p(int stage, const RhsArgs<TC>& a, hipStream_t s) {
+  switch (stage) {
+    case kStageE1: return launch_rhs_t<TI, TC, TO, P, kStageE1>(a, s);
+    case kStageE2: return launch_rhs_t<TI, TC, TO, P, kStageE2>(a, s);
+    case kStageH1: return launch_rhs_t<TI, TC, TO, P, kStageH1>(a, s);
+    case kStageH2: return launch_rhs_t<TI, TC, TO, P, kStageH2>(a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int P>
+hipError_t launch_res_p(int stage, const RhsArgs<double>& a, hipStream_t s) {
+  switch (stage) {
+    case kStageR1: return launch_rhs_t<float, double, float, P, kStageR1>(a, s);
+    case kStageR2: return launch_rhs_t<float, double, float, P, kStageR2>(a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename TI, typename TC, typename TO>
+hipError_t launch_rhs_any(int stage, int p, const RhsArgs<TC>& a, hipStream_t s) {
+  switch (p) {
+    case 1: return launch_rhs_p<TI, TC, TO, 1>(stage, a, s);
+    case 2: return launch_rhs_p<TI, TC, TO, 2>(stage, a, s);
+    case 3: return launch_rhs_p<TI, TC, TO, 3>(stage, a, s);
+    case 4: return launch_rhs_p<TI, TC, TO, 4>(stage, a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename T, int P>
+hipError_t launch_sweep_p(int ndesc, const SweepArgs& a, hipStream_t s) {
+  const size_t lds = size_t(a.n) * kPitch * sizeof(T);
+  dim3 grid((a.nlines + 63) / 64, ndesc);
+  if (a.xaxis) {
+    auto k = sweep_kernel<T, P, true>;
+    hipError_t e = set_lds(k, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k, grid, dim3(64), lds, s, a);
+  } else {
+    auto k = sweep_kernel<T, P, false>;
+    hipError_t e = set_lds(k, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k, grid, dim3(64), lds, s, a);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_rhs(int stage, int p, const RhsArgs<T>& a, hipStream_t s) {
+  return launch_rhs_any<T, T, T>(stage, p, a, s);
+}
+template hipError_t launch_rhs<double>(int, int, const RhsArgs<double>&, hipStream_t);
+template hipError_t launch_rhs<float>(int, int, const RhsArgs<float>&, hipStream_t);
+
+// float64 residual of the float32 E solve: inputs float32, arithmetic float64,
+// output float32 (the residual is small; float32 keeps ~7 digits of it).
+hipError_t launch_residual(int stage, int p, const RhsArgs<double>& a, hipStream_t s) {
+  switch (p) {
+    case 1: return launch_res_p<1>(stage, a, s);
+    case 2: return launch_res_p<2>(stage, a, s);
+    case 3: return launch_res_p<3>(stage, a, s);
+    case 4: return launch_res_p<4>(stage, a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t launch_sweep(int p, int ndesc, const SweepArgs& a, hipStream_t s) {
+  switch (p) {
+    case 1: return launch_sweep_p<T, 1>(ndesc, a, s);
+    case 2: return launch_sweep_p<T, 2>(ndesc, a, s);
+    case 3: return launch_sweep_p<T, 3>(ndesc, a, s);
+    case 4: return launch_sweep_p<T, 4>(ndesc, a, s);
+  }
+  return hipErrorInvalidValue;
+}
+template hipError_t launch_sweep<double>(int, int, const SweepArgs&, hipStream_t);
+template hipError_t launch_sweep<float>(int, int, const SweepArgs&, hipStream_t);
+
+hipError_t launch_factor(int p, const FactorArgs& a, hipStream_t s) {
+  dim3 grid((a.nlines + 63) / 64);
+  switch (p) {
+    case 1: hipLaunchKernelGGL(factor_kernel<1>, grid, dim3(64), 0, s, a); break;
+    case 2: hipLaunchKernelGGL(factor_kernel<2>, grid, dim3(64), 0, s, a); break;
+    case 3: hipLaunchKernelGGL(factor_kernel<3>, grid, dim3(64), 0, s, a); break;
+    case 4: hipLaunchKernelGGL(factor_kernel<4>, grid, dim3(64), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// dir 0: double -> float, dir 1: float -> double
+template <typename T>
+hipError_t launch_convert(const void* src, void* dst, size_t count, int dir, hipStream_t s) {
+  const int blocks = int(std::min<size_t>((count + 255) / 256, 4096));
+  if (count == 0) return hipSuccess;
+  if (dir == 0) {
+    auto k = convert_kernel<double, float>;
+    hipLaunchKernelGGL(k, dim3(blocks), dim3(256), 0, s, static_cast<const double*>(src),
+                       static_cast<float*>(dst), count);
+  } else {
+    auto k = convert_kernel<float, double>;
+    hipLaunchKernelGGL(k, dim3(blocks), dim3(256), 0, s, static_cast<const float*>(src),
+                       static_cast<double*>(dst), count);
+  }
+  return hipGetLastError();
+}
+template hipError_t launch_convert<float>(const void*, void*, size_t, int, hipStream_t);
+
+}  // namespace adimx

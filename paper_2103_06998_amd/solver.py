@@ -1,0 +1,131 @@
+"""Object API over the libadimx C ABI.
+
+PyTorch is used only for device memory (the workspace tensor the library
+carves its buffers from) and for the HIP stream the library enqueues on.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _lib
+
+PRECISIONS = {"fp64": _lib.ADI_FP64, "fp32_refine": _lib.ADI_FP32_REFINE}
+
+
+class Solver:
+    """ADI time stepper for an N^3-element patch of degree-p B-splines.
+
+    Parameters
+    ----------
+    N, p : elements per axis and B-spline degree (1 <= p <= 4).
+    precision : "fp64" or "fp32_refine".
+    device : torch device string; its current stream is used.
+    """
+
+    def __init__(self, N: int, p: int, precision: str = "fp64", device: str = "cuda:0",
+                 stream=None):
+        import torch
+
+        self.lib = _lib.load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the ADI step runs only in the HIP library")
+        self.N, self.p = int(N), int(p)
+        self.n = self.N + self.p
+        self.precision = precision
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        st = self.lib.adi_create(ctypes.byref(h), self.N, self.N, self.N, self.p,
+                                 PRECISIONS[precision], ctypes.c_void_p(self.stream.cuda_stream))
+        if st != 0:
+            raise _lib.AdiError(st, "adi_create")
+        self.h = h
+        nbytes = int(self.lib.adi_workspace_bytes(self.h))
+        with torch.cuda.device(self.device):
+            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self._check(self.lib.adi_bind_workspace(self.h, ctypes.c_void_p(self.workspace.data_ptr()),
+                                                nbytes))
+
+    # -- helpers -------------------------------------------------------------
+    def _check(self, st: int):
+        if st != 0:
+            msg = self.lib.adi_last_error(self.h).decode()
+            raise _lib.AdiError(st, msg)
+
+    def _arr(self, a, count=None):
+        a = np.ascontiguousarray(a, dtype=np.float64)
+        if count is not None and a.size != count:
+            raise ValueError(f"expected {count} values, got {a.size}")
+        return a
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.adi_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- setup ---------------------------------------------------------------
+    def set_material(self, eps_r, mu_r, sigma_nd):
+        """Voxel material map (arrays shaped (Vz, Vy, Vx)); Greville sampling."""
+        e, m, s = (self._arr(v) for v in (eps_r, mu_r, sigma_nd))
+        Vz, Vy, Vx = np.shape(eps_r)
+        self._check(self.lib.adi_set_material(self.h, _lib.dptr(e), _lib.dptr(m), _lib.dptr(s),
+                                              Vx, Vy, Vz, _lib.ADI_MAP_GREVILLE))
+
+    def set_material_dof(self, eps, mu, sigma_nd):
+        D = self.n ** 3
+        e, m, s = (self._arr(np.broadcast_to(np.asarray(v, float), (self.n,) * 3), D)
+                   for v in (eps, mu, sigma_nd))
+        self._check(self.lib.adi_set_material_dof(self.h, _lib.dptr(e), _lib.dptr(m), _lib.dptr(s)))
+
+    def set_source(self, xs, comp=0, amp=1.0, f0=2.0, t0=0.5, width=0.2):
+        x = self._arr(xs, 3)
+        self._check(self.lib.adi_set_source(self.h, _lib.dptr(x), int(comp), float(amp),
+                                            float(f0), float(t0), float(width)))
+
+    def factor(self, dt: float):
+        self._check(self.lib.adi_factor(self.h, float(dt)))
+
+    # -- state ---------------------------------------------------------------
+    def set_fields(self, EH, t: float = 0.0):
+        a = self._arr(EH, 6 * self.n ** 3)
+        self._check(self.lib.adi_set_fields(self.h, _lib.dptr(a), float(t)))
+
+    def get_fields(self):
+        out = np.empty((6, self.n, self.n, self.n))
+        t = ctypes.c_double()
+        self._check(self.lib.adi_get_fields(self.h, _lib.dptr(out), ctypes.byref(t)))
+        return out, t.value
+
+    def step(self, nsteps: int = 1):
+        self._check(self.lib.adi_step(self.h, int(nsteps)))
+
+    def sync(self):
+        self._check(self.lib.adi_sync(self.h))
+
+    def fields_device(self):
+        ptr = ctypes.c_void_p()
+        dt = ctypes.c_int()
+        self._check(self.lib.adi_fields_device(self.h, ctypes.byref(ptr), ctypes.byref(dt)))
+        return ptr.value, ("float64" if dt.value == 0 else "float32")
+
+    # -- single stages (testing) ---------------------------------------------
+    def rhs(self, stage: int, sub: int, fields, t: float = 0.0):
+        nf = 6 if stage == 0 else 9
+        a = self._arr(fields, nf * self.n ** 3)
+        out = np.empty((3, self.n, self.n, self.n))
+        self._check(self.lib.adi_rhs(self.h, int(stage), int(sub), _lib.dptr(a), float(t),
+                                     _lib.dptr(out)))
+        return out
+
+    def solve(self, stage: int, sub: int, rhs):
+        a = self._arr(rhs, 3 * self.n ** 3).copy()
+        self._check(self.lib.adi_solve(self.h, int(stage), int(sub), _lib.dptr(a)))
+        return a.reshape(3, self.n, self.n, self.n)
