@@ -129,6 +129,22 @@ int adi_fields_device(adi_ctx* ctx, void** dev, int* dtype);
 /* Wait for all work enqueued by the context. */
 int adi_sync(adi_ctx* ctx);
 
+/*
+ * Per-kernel timing of the step.  adi_profile_run enqueues nsteps full steps
+ * on the context's stream without the graph, with a pair of HIP events
+ * around every kernel launch, waits after each step and accumulates every
+ * launch's duration (the state advances by nsteps steps).  adi_profile_read
+ * reports, for each launch of a step in launch order: its kind (0 = E
+ * right-hand side, 1 = H right-hand side, 2 = float64 residual, 3 = x-line
+ * solves, 4 = y/z-line solves), the number of field components it processes,
+ * how many of those use per-line (material-modified) factors, and its mean
+ * duration in milliseconds.  *nout receives the number of launches per step
+ * (the arrays hold cap entries).
+ */
+int adi_profile_run(adi_ctx* ctx, int nsteps);
+int adi_profile_read(adi_ctx* ctx, int cap, int* nout, int* kind, int* ndesc, int* nmod,
+                     float* ms);
+
 const char* adi_last_error(const adi_ctx* ctx);
 void adi_destroy(adi_ctx* ctx);
 

@@ -65,6 +65,8 @@ struct adi_ctx {
   double* coef64[4] = {};   // float64 copies (refine mode), else alias of coefT
   void* bandT = nullptr;    // [M,A,B,S][n][2p+1] in the field type
   double* band64 = nullptr; // same in float64
+  void* zwT = nullptr;      // z weights [M,A,B,S][k][2p+1] in the field type
+  double* zw64 = nullptr;   // same in float64
   double* fb64 = nullptr;   // factor bands: Mdir, Sdir (n (2p+1) each)
   void* shL[2] = {}, *shU[2] = {}, *shD[2] = {};  // shared factors: [0] free, [1] Dirichlet
   void* mL[6] = {}, *mU[6] = {}, *mD[6] = {};     // per-line factors, system (s-1)*3 + c
@@ -74,6 +76,15 @@ struct adi_ctx {
 
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+
+  // per-launch timing (eager profiling pass): events recorded around every
+  // kernel of a step, durations summed over the profiled steps
+  bool profiling = false;
+  std::vector<hipEvent_t> events;      // 2 per launch
+  std::vector<int> launch_kind, launch_ndesc, launch_nmod;
+  std::vector<double> launch_ms_sum;
+  int profiled_steps = 0;
+  size_t launch_idx = 0;
 
   bool refine() const { return prec == ADI_FP32_REFINE; }
 };
@@ -112,6 +123,8 @@ size_t layout(adi_ctx* c, unsigned char* base) {
                                : reinterpret_cast<double*>(c->coefT[i]);
   c->bandT = take(size_t(4) * n * W * es);
   c->band64 = reinterpret_cast<double*>(take(size_t(4) * n * W * 8));
+  c->zwT = take(size_t(4) * n * W * es);
+  c->zw64 = reinterpret_cast<double*>(take(size_t(4) * n * W * 8));
   c->fb64 = reinterpret_cast<double*>(take(size_t(2) * n * W * 8));
   for (int v = 0; v < 2; ++v) {
     c->shL[v] = take(size_t(n) * P * es);
@@ -149,6 +162,34 @@ int upload(adi_ctx* c, void* dst, const std::vector<double>& src) {
 }
 
 // ---------------------------------------------------------------- enqueue
+enum LaunchKind { kKindRhsE = 0, kKindRhsH = 1, kKindResidual = 2, kKindSweepX = 3, kKindSweepYZ = 4 };
+
+// Run `launch` on stream s; when profiling, bracket it with two events.
+template <typename F>
+hipError_t timed(adi_ctx* c, hipStream_t s, int kind, int ndesc, int nmod, F&& launch) {
+  if (!c->profiling) return launch();
+  const size_t i = c->launch_idx++;
+  while (c->events.size() < 2 * (i + 1)) {
+    hipEvent_t e;
+    hipError_t err = hipEventCreate(&e);
+    if (err != hipSuccess) return err;
+    c->events.push_back(e);
+  }
+  if (c->launch_kind.size() < i + 1) {
+    c->launch_kind.resize(i + 1);
+    c->launch_ndesc.resize(i + 1);
+    c->launch_nmod.resize(i + 1);
+  }
+  c->launch_kind[i] = kind;
+  c->launch_ndesc[i] = ndesc;
+  c->launch_nmod[i] = nmod;
+  hipError_t e = hipEventRecord(c->events[2 * i], s);
+  if (e != hipSuccess) return e;
+  e = launch();
+  if (e != hipSuccess) return e;
+  return hipEventRecord(c->events[2 * i + 1], s);
+}
+
 template <typename T>
 RhsArgs<T> rhs_args(adi_ctx* c, const void* const* f, int nf, void* const* out, int kindH,
                     int sub) {
@@ -163,8 +204,8 @@ RhsArgs<T> rhs_args(adi_ctx* c, const void* const* f, int nf, void* const* out, 
     a.coef[2] = static_cast<const T*>(c->coefT[0]);  // alpha
   }
   a.band = static_cast<const T*>(c->bandT);
+  a.zw = static_cast<const T*>(c->zwT);
   a.n = c->n;
-  a.zchunk = 32;
   a.src = c->src;
   a.tnow = c->d_t;
   a.frac_dt = (sub == 1 ? 0.25 : 0.75) * c->dt;
@@ -237,7 +278,10 @@ hipError_t enqueue_solves(adi_ctx* c, int kindH, int sub, void* buf, void* final
       a.nlines = c->n * c->n;
       a.xaxis = xgroup;
       a.tick_t = nullptr;
-      hipError_t e = launch_sweep<T>(c->p, nd, a, s);
+      int nmod = 0;
+      for (int q = 0; q < nd; ++q) nmod += a.d[q].modified;
+      hipError_t e = timed(c, s, xgroup ? kKindSweepX : kKindSweepYZ, nd, nmod,
+                           [&] { return launch_sweep<T>(c->p, nd, a, s); });
       if (e != hipSuccess) return e;
     }
   }
@@ -259,7 +303,9 @@ hipError_t enqueue_step_t(adi_ctx* c, hipStream_t s) {
                           comp(Hin, 0, c), comp(Hin, 1, c), comp(Hin, 2, c)};
       void* out[3] = {comp(Eout, 0, c), comp(Eout, 1, c), comp(Eout, 2, c)};
       RhsArgs<T> a = rhs_args<T>(c, f, 6, out, 0, sub);
-      hipError_t e = launch_rhs<T>(sub == 1 ? kStageE1 : kStageE2, c->p, a, s);
+      hipError_t e = timed(c, s, kKindRhsE, 3, 0, [&] {
+        return launch_rhs<T>(sub == 1 ? kStageE1 : kStageE2, c->p, a, s);
+      });
       if (e != hipSuccess) return e;
       e = enqueue_solves<T>(c, 0, sub, Eout, nullptr, s);
       if (e != hipSuccess) return e;
@@ -274,12 +320,14 @@ hipError_t enqueue_step_t(adi_ctx* c, hipStream_t s) {
         r.coef[1] = c->coef64[1];
         r.coef[2] = c->coef64[0];
         r.band = c->band64;
+        r.zw = c->zw64;
         r.n = c->n;
-        r.zchunk = 32;
         r.src = c->src;
         r.tnow = c->d_t;
         r.frac_dt = (sub == 1 ? 0.25 : 0.75) * c->dt;
-        e = launch_residual(sub == 1 ? kStageR1 : kStageR2, c->p, r, s);
+        e = timed(c, s, kKindResidual, 3, 0, [&] {
+          return launch_residual(sub == 1 ? kStageR1 : kStageR2, c->p, r, s);
+        });
         if (e != hipSuccess) return e;
         e = enqueue_solves<float>(c, 0, sub, c->R32, Eout, s);
         if (e != hipSuccess) return e;
@@ -292,7 +340,9 @@ hipError_t enqueue_step_t(adi_ctx* c, hipStream_t s) {
                           comp(Eout, 0, c), comp(Eout, 1, c), comp(Eout, 2, c)};
       void* out[3] = {comp(Hout, 0, c), comp(Hout, 1, c), comp(Hout, 2, c)};
       RhsArgs<T> a = rhs_args<T>(c, f, 9, out, 1, sub);
-      hipError_t e = launch_rhs<T>(sub == 1 ? kStageH1 : kStageH2, c->p, a, s);
+      hipError_t e = timed(c, s, kKindRhsH, 3, 0, [&] {
+        return launch_rhs<T>(sub == 1 ? kStageH1 : kStageH2, c->p, a, s);
+      });
       if (e != hipSuccess) return e;
       // H: x, y, z (all shared factors); the last launch advances the time
       for (int ax = 0; ax < 3; ++ax) {
@@ -308,7 +358,8 @@ hipError_t enqueue_step_t(adi_ctx* c, hipStream_t s) {
           w.tick_t = c->d_t;
           w.tick_dt = c->dt;
         }
-        e = launch_sweep<T>(c->p, 3, w, s);
+        e = timed(c, s, ax == 0 ? kKindSweepX : kKindSweepYZ, 3, 0,
+                  [&] { return launch_sweep<T>(c->p, 3, w, s); });
         if (e != hipSuccess) return e;
       }
     }
@@ -329,6 +380,7 @@ void drop_graph(adi_ctx* c) {
 
 int capture(adi_ctx* c) {
   drop_graph(c);
+  c->launch_idx = 0;
   HIPCHK(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeRelaxed));
   hipError_t e = enqueue_step(c, c->cap);
   hipGraph_t g = nullptr;
@@ -527,6 +579,17 @@ int adi_factor(adi_ctx* c, double dt) {
   std::copy(g.S.begin(), g.S.end(), ops.begin() + size_t(3) * n * W);
   if ((st = upload(c, c->bandT, ops)) != ADI_OK) return st;
   HIPCHK(c, hipMemcpy(c->band64, ops.data(), ops.size() * 8, hipMemcpyHostToDevice));
+  // z weights: input plane k contributes Z[k-p+q][k] to output plane k-p+q
+  std::vector<double> zw(size_t(4) * n * W, 0.0);
+  for (int op = 0; op < 4; ++op)
+    for (int k = 0; k < n; ++k)
+      for (int q = 0; q < W; ++q) {
+        const int t = k - p + q;
+        if (t < 0 || t >= n) continue;
+        zw[(size_t(op) * n + k) * W + q] = ops[(size_t(op) * n + t) * W + (k - t + p)];
+      }
+  if ((st = upload(c, c->zwT, zw)) != ADI_OK) return st;
+  HIPCHK(c, hipMemcpy(c->zw64, zw.data(), zw.size() * 8, hipMemcpyHostToDevice));
 
   // shared factors of M (free) and M with Dirichlet rows/columns
   for (int v = 0; v < 2; ++v) {
@@ -535,6 +598,8 @@ int adi_factor(adi_ctx* c, double dt) {
     std::vector<double> L, U, Dinv;
     const double r = band_lu(band, n, p, L, U, Dinv);
     if (!(r > 1e-14)) return fail(c, ADI_ESINGULAR, "singular mass matrix factor");
+    for (int i = 0; i < n; ++i)  // pre-scale the upper factor: D * U
+      for (int k = 0; k < p; ++k) U[size_t(i) * p + k] *= Dinv[i];
     if ((st = upload(c, c->shL[v], L)) != ADI_OK) return st;
     if ((st = upload(c, c->shU[v], U)) != ADI_OK) return st;
     if ((st = upload(c, c->shD[v], Dinv)) != ADI_OK) return st;
@@ -667,12 +732,62 @@ int adi_sync(adi_ctx* c) {
   return ADI_OK;
 }
 
+int adi_profile_run(adi_ctx* c, int nsteps) {
+  if (!c || nsteps < 1) return ADI_EINVAL;
+  if (!c->factored) return fail(c, ADI_ESTATE, "adi_factor must succeed before profiling");
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->profiling = true;
+  c->launch_ms_sum.clear();
+  c->profiled_steps = 0;
+  int st = ADI_OK;
+  for (int k = 0; k < nsteps && st == ADI_OK; ++k) {
+    c->launch_idx = 0;
+    hipError_t e = enqueue_step(c, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+      st = fail(c, ADI_EHIP, std::string("profiled step: ") + hipGetErrorString(e));
+      break;
+    }
+    const size_t n = c->launch_idx;
+    c->launch_ms_sum.resize(n, 0.0);
+    for (size_t i = 0; i < n; ++i) {
+      float ms = 0.f;
+      e = hipEventElapsedTime(&ms, c->events[2 * i], c->events[2 * i + 1]);
+      if (e != hipSuccess) {
+        st = fail(c, ADI_EHIP, std::string("hipEventElapsedTime: ") + hipGetErrorString(e));
+        break;
+      }
+      c->launch_ms_sum[i] += ms;
+    }
+    ++c->profiled_steps;
+  }
+  c->profiling = false;
+  c->t += c->profiled_steps * c->dt;
+  return st;
+}
+
+int adi_profile_read(adi_ctx* c, int cap, int* nout, int* kind, int* ndesc, int* nmod,
+                     float* ms) {
+  if (!c || !nout) return ADI_EINVAL;
+  if (c->profiled_steps == 0) return fail(c, ADI_ESTATE, "run adi_profile_run first");
+  const int n = int(c->launch_ms_sum.size());
+  *nout = n;
+  for (int i = 0; i < n && i < cap; ++i) {
+    if (kind) kind[i] = c->launch_kind[i];
+    if (ndesc) ndesc[i] = c->launch_ndesc[i];
+    if (nmod) nmod[i] = c->launch_nmod[i];
+    if (ms) ms[i] = float(c->launch_ms_sum[i] / c->profiled_steps);
+  }
+  return ADI_OK;
+}
+
 const char* adi_last_error(const adi_ctx* c) { return c ? c->err.c_str() : "invalid handle"; }
 
 void adi_destroy(adi_ctx* c) {
   if (!c) return;
   if (c->stream) hipStreamSynchronize(c->stream);
   drop_graph(c);
+  for (hipEvent_t e : c->events) hipEventDestroy(e);
   if (c->own_ws && c->ws) hipFree(c->ws);
   if (c->cap) hipStreamDestroy(c->cap);
   delete c;

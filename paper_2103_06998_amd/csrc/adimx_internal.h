@@ -55,8 +55,9 @@ struct RhsArgs {
   void* out[3];           // T (or float for the residual in refine mode)
   const T* coef[3];       // E: gamma, beta, alpha ; H: delta
   const T* band;          // [op][r][2p+1], op 0 = M, 1 = A, 2 = B, 3 = S
+  const T* zw;            // [op][k][2p+1]: weight of input plane k on output plane
+                          // k - p + q (band entry Z[k-p+q][k], zero outside)
   int n;
-  int zchunk;
   SourceArgs src;
   const double* tnow;     // device time at the start of the step
   double frac_dt;         // (1/4 or 3/4) * dt
@@ -68,7 +69,7 @@ struct SweepDesc {
   void* out;              // solution (T); may equal in
   const void* acc;        // if non-null, out = solution + acc (element-wise)
   const void* L;          // factors; shared: [r*P + k-1], modified: [((k-1)*n + r)*nlines + l]
-  const void* U;
+  const void* U;          // D * U (pre-scaled upper factor), same layout as L
   const void* D;          // inverse diagonal; shared: [r], modified: [r*nlines + l]
   int modified;           // 0 = shared factors, 1 = per-line factors
 };
@@ -86,7 +87,7 @@ struct FactorArgs {
   const double* Mb;       // band of the base matrix (Dirichlet rows applied)
   const double* Sb;       // band of the stiffness matrix (Dirichlet rows/cols zero)
   const double* alpha;    // per-DOF coefficient (n^3, x fastest)
-  double* L64; double* U64; double* D64;   // per-line factors (float64)
+  double* L64; double* U64; double* D64;   // per-line factors (float64): L, D*U, D
   float* L32; float* U32; float* D32;      // float32 copies (refine mode) or null
   double* minratio;       // per line: min |U_rr| / |A_rr|
   int n, nlines, axis;

@@ -111,45 +111,54 @@ __device__ __forceinline__ void static_for(F&& f) {
   static_for_impl<N>(f, std::make_integer_sequence<int, N>{});
 }
 
-constexpr int kTX = 32, kTY = 8, kRhsThreads = kTX * kTY;
+constexpr int kTX = 32, kTY = 8, kCols = kTX * kTY;
+constexpr int kRhsThreads = 3 * kCols;  // one group of 4 waves per output component
+constexpr int kZChunk = 32;             // output planes per block
 
 template <typename TC, int P, int STAGE>
 constexpr size_t rhs_lds_bytes() {
   constexpr int W = 2 * P + 1, HX = kTX + 2 * P, HY = kTY + 2 * P;
   constexpr PairTab PT = make_pairs<STAGE>();
   return sizeof(TC) * (size_t(StageInfo<STAGE>::NF) * HY * HX + size_t(PT.np) * kTY * HX +
-                       4 * kTX * W + 4 * kTY * W);
+                       4 * kTX * W + 4 * kTY * W + 4 * (kZChunk + 2 * P) * W);
 }
 
 // ------------------------------------------------------------ RHS kernel
-// Block = a kTX x kTY tile of (x, y) output columns and a chunk of z planes.
-// Input planes are marched along z: each plane of every input field is
-// staged (with a p-halo in x and y) in LDS, the y operators then the x
-// operators are applied in the plane, and the result is scattered into a
-// register queue of 2p+1 pending output planes with the z operator's
-// weights.  When the oldest pending plane is complete it is scaled by the
-// per-row coefficients and written.  TI: input type, TC: arithmetic type,
-// TO: output type.
+// Block = a kTX x kTY tile of (x, y) output columns and a chunk of kZChunk z
+// planes; its three groups of 256 threads compute the three output
+// components.  Input planes are marched along z: each plane of every input
+// field is staged (with a p-halo in x and y) in LDS (the next plane is
+// loaded into registers while the current one is processed), the y operators
+// and then the x operators are applied in the plane, and each result is
+// scattered into a register queue of 2p+1 pending output planes with the z
+// operator's weights.  When the oldest pending plane is complete it is scaled
+// by the per-row coefficients and written.  TI: input type, TC: arithmetic
+// type, TO: output type.
 template <typename TI, typename TC, typename TO, int P, int STAGE>
 __global__ __launch_bounds__(kRhsThreads) void rhs_kernel(RhsArgs<TC> a) {
-  constexpr int W = 2 * P + 1, HX = kTX + 2 * P, HY = kTY + 2 * P;
+  constexpr int W = 2 * P + 1, HX = kTX + 2 * P, HY = kTY + 2 * P, ZR = kZChunk + 2 * P;
   constexpr int NT = StageInfo<STAGE>::NT, NF = StageInfo<STAGE>::NF, NG = StageInfo<STAGE>::NG;
   constexpr PairTab PT = make_pairs<STAGE>();
   constexpr int NP = PT.np;
   constexpr bool kE = !(STAGE == kStageH1 || STAGE == kStageH2);
+  constexpr int PLANE = NF * HY * HX;                          // staged values per plane
+  constexpr int NLD = (PLANE + kRhsThreads - 1) / kRhsThreads;  // per thread
 
   extern __shared__ __align__(16) unsigned char smem[];
   TC* sF = reinterpret_cast<TC*>(smem);
-  TC* sG = sF + NF * HY * HX;
+  TC* sG = sF + PLANE;
   TC* sBX = sG + NP * kTY * HX;
   TC* sBY = sBX + 4 * kTX * W;
+  TC* sZ = sBY + 4 * kTY * W;  // [op][k - (t0 - P)][q]
 
   const int n = a.n;
   const size_t plane = size_t(n) * n;
-  const int tid = threadIdx.x, tx = tid % kTX, ty = tid / kTX;
+  const int tid = threadIdx.x;
+  const int comp = tid / kCols;  // uniform per wave
+  const int cid = tid % kCols, tx = cid % kTX, ty = cid / kTX;
   const int i0 = blockIdx.x * kTX, j0 = blockIdx.y * kTY;
-  const int t0 = blockIdx.z * a.zchunk;
-  const int t1 = min(n, t0 + a.zchunk);
+  const int t0 = blockIdx.z * kZChunk;
+  const int t1 = min(n, t0 + kZChunk);
   const TC* band = a.band;
 
   for (int idx = tid; idx < 4 * kTX * W; idx += kRhsThreads) {
@@ -162,33 +171,65 @@ __global__ __launch_bounds__(kRhsThreads) void rhs_kernel(RhsArgs<TC> a) {
     const int gj = j0 + r;
     sBY[idx] = gj < n ? band[(size_t(op) * n + gj) * W + d] : TC(0);
   }
+  // z weights of the planes this block reads: zw[(op*n + k)*W + q] is the
+  // weight of input plane k on output plane k - p + q (zero outside)
+  for (int idx = tid; idx < 4 * ZR * W; idx += kRhsThreads) {
+    const int op = idx / (ZR * W), rem = idx % (ZR * W), kk = rem / W, q = rem % W;
+    const int k = t0 - P + kk;
+    sZ[idx] = (k >= 0 && k < n) ? a.zw[(size_t(op) * n + k) * W + q] : TC(0);
+  }
 
-  TC acc[3 * NG][W];
+  // Offsets of this thread's staged values within a plane (-1: outside the
+  // patch, staged as zero) and the field they come from.
+  int goff[NLD], gfld[NLD];
 #pragma unroll
-  for (int g = 0; g < 3 * NG; ++g)
+  for (int u = 0; u < NLD; ++u) {
+    const int idx = tid + u * kRhsThreads;
+    goff[u] = -1;
+    gfld[u] = 0;
+    if (idx < PLANE) {
+      const int f = idx / (HY * HX), rem = idx % (HY * HX), yy = rem / HX, xx = rem % HX;
+      const int gi = i0 - P + xx, gj = j0 - P + yy;
+      gfld[u] = f;
+      if (gi >= 0 && gi < n && gj >= 0 && gj < n) goff[u] = gi + n * gj;
+    }
+  }
+  auto load_plane = [&](int k, TC (&v)[NLD]) {
+#pragma unroll
+    for (int u = 0; u < NLD; ++u) {
+      v[u] = TC(0);
+      if (goff[u] >= 0)
+        v[u] = TC(static_cast<const TI*>(a.f[gfld[u]])[size_t(goff[u]) + plane * size_t(k)]);
+    }
+  };
+
+  TC acc[NG][W];
+#pragma unroll
+  for (int g = 0; g < NG; ++g)
 #pragma unroll
     for (int q = 0; q < W; ++q) acc[g][q] = TC(0);
 
   // source value at the midpoint of the substep (uniform)
   double jsrc = 0.0;
-  if (kE && a.src.comp >= 0) {
+  if (kE && a.src.comp == comp) {
     const double tm = *a.tnow + a.frac_dt;
     const double s = tm - a.src.t0;
     jsrc = a.src.amp * sin(2.0 * 3.14159265358979323846 * a.src.f0 * s) *
            exp(-(s / a.src.width) * (s / a.src.width));
   }
 
+  const int kbeg = max(t0 - P, 0), kend = min(t1 + P, n);  // input planes to read
+  TC pre[NLD];
+  load_plane(kbeg, pre);
   for (int k = t0 - P; k < t1 + P; ++k) {
-    if (k >= 0 && k < n) {
-      __syncthreads();
-      for (int idx = tid; idx < NF * HY * HX; idx += kRhsThreads) {
-        const int f = idx / (HY * HX), rem = idx % (HY * HX), yy = rem / HX, xx = rem % HX;
-        const int gi = i0 - P + xx, gj = j0 - P + yy;
-        TC v = TC(0);
-        if (gi >= 0 && gi < n && gj >= 0 && gj < n)
-          v = TC(static_cast<const TI*>(a.f[f])[gi + size_t(n) * gj + plane * k]);
-        sF[idx] = v;
+    if (k >= kbeg && k < kend) {
+      __syncthreads();  // the previous plane's passes are done with sF / sG
+#pragma unroll
+      for (int u = 0; u < NLD; ++u) {
+        const int idx = tid + u * kRhsThreads;
+        if (idx < PLANE) sF[idx] = pre[u];
       }
+      if (k + 1 < kend) load_plane(k + 1, pre);  // in flight during this plane
       __syncthreads();
       static_for<NP>([&](auto pc) {
         constexpr int pr = decltype(pc)::value;
@@ -202,18 +243,18 @@ __global__ __launch_bounds__(kRhsThreads) void rhs_kernel(RhsArgs<TC> a) {
         }
       });
       __syncthreads();
+      const TC* zk = sZ + (k - (t0 - P)) * W;
       static_for<NT>([&](auto ic) {
         constexpr int it = decltype(ic)::value;
         constexpr Term tm = get_term<STAGE>(it);
         constexpr int pr = PT.of_term[it];
-        TC v = TC(0);
+        if (tm.out == comp) {
+          TC v = TC(0);
 #pragma unroll
-        for (int d = 0; d < W; ++d) v += sBX[(tm.x * kTX + tx) * W + d] * sG[(pr * kTY + ty) * HX + tx + d];
-        if (tm.sign < 0) v = -v;
+          for (int d = 0; d < W; ++d) v += sBX[(tm.x * kTX + tx) * W + d] * sG[(pr * kTY + ty) * HX + tx + d];
+          if (tm.sign < 0) v = -v;
 #pragma unroll
-        for (int q = 0; q < W; ++q) {
-          const int t = k - P + q;
-          if (t >= 0 && t < n) acc[tm.out * NG + tm.grp][q] += band[(size_t(tm.z) * n + t) * W + (k - t + P)] * v;
+          for (int q = 0; q < W; ++q) acc[tm.grp][q] += zk[tm.z * ZR * W + q] * v;
         }
       });
     }
@@ -226,33 +267,26 @@ __global__ __launch_bounds__(kRhsThreads) void rhs_kernel(RhsArgs<TC> a) {
                    bk = (te == 0 || te == n - 1);
         if (kE) {
           const TC g = a.coef[0][o], b = a.coef[1][o], al = a.coef[2][o];
-#pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            TC v = g * acc[c * NG + 0][0] + b * acc[c * NG + 1][0] + al * acc[c * NG + 2][0];
-            if (NG == 4) v += acc[c * NG + (NG - 1)][0];
-            if (c == a.src.comp) {
-              const int ri = i - a.src.first[0], rj = j - a.src.first[1], rk = te - a.src.first[2];
-              if (ri >= 0 && ri <= P && rj >= 0 && rj <= P && rk >= 0 && rk <= P)
-                v -= b * TC(jsrc * (a.src.bz[rk] * a.src.by[rj] * a.src.bx[ri]));
-            }
-            // E_c is constrained on the faces normal to the two other axes
-            const bool bnd = (c == 0) ? (bj || bk) : (c == 1) ? (bi || bk) : (bi || bj);
-            static_cast<TO*>(a.out[c])[o] = bnd ? TO(0) : TO(v);
+          TC v = g * acc[0][0] + b * acc[1][0] + al * acc[2][0];
+          if (NG == 4) v += acc[NG - 1][0];
+          if (comp == a.src.comp) {
+            const int ri = i - a.src.first[0], rj = j - a.src.first[1], rk = te - a.src.first[2];
+            if (ri >= 0 && ri <= P && rj >= 0 && rj <= P && rk >= 0 && rk <= P)
+              v -= b * TC(jsrc * (a.src.bz[rk] * a.src.by[rj] * a.src.bx[ri]));
           }
+          // E_c is constrained on the faces normal to the two other axes
+          const bool bnd = (comp == 0) ? (bj || bk) : (comp == 1) ? (bi || bk) : (bi || bj);
+          static_cast<TO*>(a.out[comp])[o] = bnd ? TO(0) : TO(v);
         } else {
-          const TC dl = a.coef[0][o];
-#pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            const TC v = acc[c * NG + 0][0] + dl * acc[c * NG + 1][0];
-            // H_c is constrained on the faces normal to axis c
-            const bool bnd = (c == 0) ? bi : (c == 1) ? bj : bk;
-            static_cast<TO*>(a.out[c])[o] = bnd ? TO(0) : TO(v);
-          }
+          const TC v = acc[0][0] + a.coef[0][o] * acc[1][0];
+          // H_c is constrained on the faces normal to axis c
+          const bool bnd = (comp == 0) ? bi : (comp == 1) ? bj : bk;
+          static_cast<TO*>(a.out[comp])[o] = bnd ? TO(0) : TO(v);
         }
       }
     }
 #pragma unroll
-    for (int g = 0; g < 3 * NG; ++g) {
+    for (int g = 0; g < NG; ++g) {
 #pragma unroll
       for (int q = 0; q < W - 1; ++q) acc[g][q] = acc[g][q + 1];
       acc[g][W - 1] = TC(0);
@@ -268,111 +302,210 @@ __global__ __launch_bounds__(kRhsThreads) void rhs_kernel(RhsArgs<TC> a) {
 // consecutive lanes on consecutive x (coalesced); lines along x are contiguous
 // in memory and are transposed through LDS.
 constexpr int kPitch = 65;
+constexpr int kLoadCH = 32;  // rows per lane loaded together when staging
+constexpr int kCH = 16;      // rows per compute chunk
 
-template <typename T, int P, bool XAX>
+// Factors: forward y_r = b_r - sum_k L[r][k] y_{r-1-k}; backward
+// x_r = D_r y_r - sum_k DU[r][k] x_{r+1+k} with DU = D * U (pre-scaled, so
+// every row adds one dependent FMA to the chain).  Shared factors are
+// [r*P + k] (L, DU) and [r] (D); per-line factors [((k*n) + r)*nlines + l].
+template <typename T, int P, bool XAX, bool MOD>
 __global__ __launch_bounds__(64) void sweep_kernel(SweepArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   T* buf = reinterpret_cast<T*>(smem);
+  T* sfac = buf + size_t(a.n) * kPitch;  // shared factors: L[n*P], DU[n*P], D[n]
   const SweepDesc& ds = a.d[blockIdx.y];
   const int n = a.n, nl = a.nlines, lane = threadIdx.x;
   const int l0 = blockIdx.x * 64, l = l0 + lane;
   const bool act = l < nl;
-  const T* in = static_cast<const T*>(ds.in);
-  T* out = static_cast<T*>(ds.out);
-  const T* accp = static_cast<const T*>(ds.acc);
+  const int nll = min(64, nl - l0);  // lines in this tile
+  const T* __restrict__ in = static_cast<const T*>(ds.in);
+  T* __restrict__ out = static_cast<T*>(ds.out);
+  const T* __restrict__ accp = static_cast<const T*>(ds.acc);
   const size_t n2 = size_t(n) * n;
-  const size_t lbase = (ds.axis == 1) ? size_t(l % n) + size_t(l / n) * n2 : size_t(l);
+  const int lc = act ? l : 0;
+  const size_t lbase = (ds.axis == 1) ? size_t(lc % n) + size_t(lc / n) * n2 : size_t(lc);
   const size_t rstride = (ds.axis == 1) ? size_t(n) : n2;
 
+  if (!MOD) {
+    const T* Lf = static_cast<const T*>(ds.L);
+    const T* Uf = static_cast<const T*>(ds.U);
+    const T* Df = static_cast<const T*>(ds.D);
+    for (int i = lane; i < n * P; i += 64) {
+      sfac[i] = Lf[i];
+      sfac[n * P + i] = Uf[i];
+    }
+    for (int i = lane; i < n; i += 64) sfac[2 * n * P + i] = Df[i];
+  }
+
+  // ---- stage the 64 x n tile in LDS: buf[r * kPitch + line]
   if (XAX) {
-    for (int ll = 0; ll < 64; ++ll) {
-      const int L = l0 + ll;
-      if (L >= nl) break;
-      const T* src = in + size_t(L) * n;
-      for (int r = lane; r < n; r += 64) buf[r * kPitch + ll] = src[r];
+    // the tile is nll * n contiguous values; lane reads elements e0 + c*64 + lane
+    const int total = nll * n;
+    const T* src = in + size_t(l0) * n;
+    const float inv_n = 1.0f / float(n);
+    for (int e0 = 0; e0 < total; e0 += 64 * kLoadCH) {
+      T v[kLoadCH];
+#pragma unroll
+      for (int c = 0; c < kLoadCH; ++c) {
+        const int e = min(e0 + c * 64 + lane, total - 1);
+        v[c] = src[e];
+      }
+#pragma unroll
+      for (int c = 0; c < kLoadCH; ++c) {
+        const int e = e0 + c * 64 + lane;
+        int ll = int((float(e) + 0.5f) * inv_n);
+        int r = e - ll * n;
+        if (r < 0) { --ll; r += n; }
+        if (r >= n) { ++ll; r -= n; }
+        if (e < total) buf[r * kPitch + ll] = v[c];
+      }
     }
   } else {
-    for (int r = 0; r < n; ++r) buf[r * kPitch + lane] = act ? in[lbase + size_t(r) * rstride] : T(0);
+    for (int r0 = 0; r0 < n; r0 += kLoadCH) {
+      T v[kLoadCH];
+#pragma unroll
+      for (int c = 0; c < kLoadCH; ++c) v[c] = in[lbase + size_t(min(r0 + c, n - 1)) * rstride];
+#pragma unroll
+      for (int c = 0; c < kLoadCH; ++c)
+        if (r0 + c < n) buf[(r0 + c) * kPitch + lane] = v[c];
+    }
   }
   __syncthreads();
 
-  if (act) {
-    const size_t fstride = size_t(n) * nl;
+  const size_t fstride = size_t(n) * nl;
+  const T* __restrict__ Lm = static_cast<const T*>(ds.L);
+  const T* __restrict__ Um = static_cast<const T*>(ds.U);
+  const T* __restrict__ Dm = static_cast<const T*>(ds.D);
+  auto fL = [&](int r, int k) -> T {
+    if (MOD) return Lm[(size_t(k) * n + r) * nl + lc];
+    return sfac[r * P + k];
+  };
+  auto fU = [&](int r, int k) -> T {
+    if (MOD) return Um[(size_t(k) * n + r) * nl + lc];
+    return sfac[n * P + r * P + k];
+  };
+  auto fD = [&](int r) -> T {
+    if (MOD) return Dm[size_t(r) * nl + lc];
+    return sfac[2 * n * P + r];
+  };
+
+  {
+    // ---- forward substitution in chunks of kCH rows (rows >= n are padding:
+    // their factors are read from row n-1 and their results are dropped)
     T h[P];
 #pragma unroll
     for (int k = 0; k < P; ++k) h[k] = T(0);
-    if (!ds.modified) {
-      const T* Ls = static_cast<const T*>(ds.L);
-      for (int r = 0; r < n; ++r) {
-        T s = buf[r * kPitch + lane];
+    T fa[kCH][P];
 #pragma unroll
-        for (int k = 0; k < P; ++k) s -= Ls[r * P + k] * h[k];
+    for (int c = 0; c < kCH; ++c)
+#pragma unroll
+      for (int k = 0; k < P; ++k) fa[c][k] = fL(min(c, n - 1), k);
+    for (int r0 = 0; r0 < n; r0 += kCH) {
+      T v[kCH], fb[kCH][P];
+#pragma unroll
+      for (int c = 0; c < kCH; ++c) v[c] = buf[min(r0 + c, n - 1) * kPitch + lane];
+#pragma unroll
+      for (int c = 0; c < kCH; ++c)
+#pragma unroll
+        for (int k = 0; k < P; ++k) fb[c][k] = fL(min(r0 + kCH + c, n - 1), k);
+#pragma unroll
+      for (int c = 0; c < kCH; ++c) {
+        T s = v[c];
+#pragma unroll
+        for (int k = P - 1; k >= 0; --k) s -= fa[c][k] * h[k];
 #pragma unroll
         for (int k = P - 1; k > 0; --k) h[k] = h[k - 1];
         h[0] = s;
-        buf[r * kPitch + lane] = s;
+        v[c] = s;
       }
-    } else {
-      const T* Lm = static_cast<const T*>(ds.L);
-      for (int r = 0; r < n; ++r) {
-        T s = buf[r * kPitch + lane];
 #pragma unroll
-        for (int k = 0; k < P; ++k) s -= Lm[k * fstride + size_t(r) * nl + l] * h[k];
+      for (int c = 0; c < kCH; ++c)
+        if (r0 + c < n) buf[(r0 + c) * kPitch + lane] = v[c];
 #pragma unroll
-        for (int k = P - 1; k > 0; --k) h[k] = h[k - 1];
-        h[0] = s;
-        buf[r * kPitch + lane] = s;
-      }
+      for (int c = 0; c < kCH; ++c)
+#pragma unroll
+        for (int k = 0; k < P; ++k) fa[c][k] = fb[c][k];
     }
+
+    // ---- backward substitution in chunks of kCH rows from the end
 #pragma unroll
     for (int k = 0; k < P; ++k) h[k] = T(0);
-    if (!ds.modified) {
-      const T* Us = static_cast<const T*>(ds.U);
-      const T* Dd = static_cast<const T*>(ds.D);
-      for (int r = n - 1; r >= 0; --r) {
-        T s = buf[r * kPitch + lane];
+    T da[kCH];
 #pragma unroll
-        for (int k = 0; k < P; ++k) s -= Us[r * P + k] * h[k];
-        s *= Dd[r];
+    for (int c = 0; c < kCH; ++c) {
+      const int r = max(n - 1 - c, 0);
 #pragma unroll
-        for (int k = P - 1; k > 0; --k) h[k] = h[k - 1];
-        h[0] = s;
-        buf[r * kPitch + lane] = s;
+      for (int k = 0; k < P; ++k) fa[c][k] = fU(r, k);
+      da[c] = fD(r);
+    }
+    for (int r0 = n - 1; r0 >= 0; r0 -= kCH) {
+      T v[kCH], fb[kCH][P], db[kCH];
+#pragma unroll
+      for (int c = 0; c < kCH; ++c) v[c] = buf[max(r0 - c, 0) * kPitch + lane];
+#pragma unroll
+      for (int c = 0; c < kCH; ++c) {
+        const int r = max(r0 - kCH - c, 0);
+#pragma unroll
+        for (int k = 0; k < P; ++k) fb[c][k] = fU(r, k);
+        db[c] = fD(r);
       }
-    } else {
-      const T* Um = static_cast<const T*>(ds.U);
-      const T* Dm = static_cast<const T*>(ds.D);
-      for (int r = n - 1; r >= 0; --r) {
-        T s = buf[r * kPitch + lane];
 #pragma unroll
-        for (int k = 0; k < P; ++k) s -= Um[k * fstride + size_t(r) * nl + l] * h[k];
-        s *= Dm[size_t(r) * nl + l];
+      for (int c = 0; c < kCH; ++c) {
+        T s = da[c] * v[c];
+#pragma unroll
+        for (int k = P - 1; k >= 0; --k) s -= fa[c][k] * h[k];
 #pragma unroll
         for (int k = P - 1; k > 0; --k) h[k] = h[k - 1];
         h[0] = s;
-        buf[r * kPitch + lane] = s;
+        v[c] = s;
+      }
+#pragma unroll
+      for (int c = 0; c < kCH; ++c)
+        if (r0 - c >= 0) buf[(r0 - c) * kPitch + lane] = v[c];
+#pragma unroll
+      for (int c = 0; c < kCH; ++c) {
+#pragma unroll
+        for (int k = 0; k < P; ++k) fa[c][k] = fb[c][k];
+        da[c] = db[c];
       }
     }
   }
   __syncthreads();
 
+  // ---- write the tile back
   if (XAX) {
-    for (int ll = 0; ll < 64; ++ll) {
-      const int L = l0 + ll;
-      if (L >= nl) break;
-      const size_t base = size_t(L) * n;
-      for (int r = lane; r < n; r += 64) {
-        T v = buf[r * kPitch + ll];
-        if (accp) v += accp[base + r];
-        out[base + r] = v;
+    const int total = nll * n;
+    T* dst = out + size_t(l0) * n;
+    const T* ac = accp ? accp + size_t(l0) * n : nullptr;
+    const float inv_n = 1.0f / float(n);
+    for (int e0 = 0; e0 < total; e0 += 64 * kLoadCH) {
+#pragma unroll
+      for (int c = 0; c < kLoadCH; ++c) {
+        const int e = e0 + c * 64 + lane;
+        int ll = int((float(e) + 0.5f) * inv_n);
+        int r = e - ll * n;
+        if (r < 0) { --ll; r += n; }
+        if (r >= n) { ++ll; r -= n; }
+        if (e < total) {
+          T v = buf[r * kPitch + ll];
+          if (ac) v += ac[e];
+          dst[e] = v;
+        }
       }
     }
   } else if (act) {
-    for (int r = 0; r < n; ++r) {
-      const size_t o = lbase + size_t(r) * rstride;
-      T v = buf[r * kPitch + lane];
-      if (accp) v += accp[o];
-      out[o] = v;
+    for (int r0 = 0; r0 < n; r0 += kLoadCH) {
+#pragma unroll
+      for (int c = 0; c < kLoadCH; ++c) {
+        const int r = r0 + c;
+        if (r < n) {
+          const size_t o = lbase + size_t(r) * rstride;
+          T v = buf[r * kPitch + lane];
+          if (accp) v += accp[o];
+          out[o] = v;
+        }
+      }
     }
   }
   if (a.tick_t && blockIdx.x == 0 && blockIdx.y == 0 && lane == 0) *a.tick_t += a.tick_dt;
@@ -432,13 +565,14 @@ __global__ __launch_bounds__(64) void factor_kernel(FactorArgs a) {
 #pragma unroll
     for (int m = 1; m <= P; ++m) {
       const size_t o = size_t(m - 1) * fstride + size_t(i) * nl + l;
+      const double du = dinv * ur[m];  // pre-scaled for the backward substitution
       if (a.L64) {
         a.L64[o] = Lr[m];
-        a.U64[o] = ur[m];
+        a.U64[o] = du;
       }
       if (a.L32) {
         a.L32[o] = float(Lr[m]);
-        a.U32[o] = float(ur[m]);
+        a.U32[o] = float(du);
       }
     }
     if (a.D64) a.D64[size_t(i) * nl + l] = dinv;
@@ -476,7 +610,7 @@ hipError_t launch_rhs_t(const RhsArgs<TC>& a, hipStream_t s) {
   hipError_t e = set_lds(k, lds);
   if (e != hipSuccess) return e;
   const int n = a.n;
-  dim3 grid((n + kTX - 1) / kTX, (n + kTY - 1) / kTY, (n + a.zchunk - 1) / a.zchunk);
+  dim3 grid((n + kTX - 1) / kTX, (n + kTY - 1) / kTY, (n + kZChunk - 1) / kZChunk);
   hipLaunchKernelGGL(k, grid, dim3(kRhsThreads), lds, s, a);
   return hipGetLastError();
 }
@@ -512,22 +646,28 @@ hipError_t launch_rhs_any(int stage, int p, const RhsArgs<TC>& a, hipStream_t s)
   return hipErrorInvalidValue;
 }
 
+template <typename T, int P, bool XAX, bool MOD>
+hipError_t launch_sweep_k(int ndesc, const SweepArgs& a, hipStream_t s) {
+  const size_t lds = (size_t(a.n) * kPitch + (MOD ? 0 : size_t(a.n) * (2 * P + 1))) * sizeof(T);
+  dim3 grid((a.nlines + 63) / 64, ndesc);
+  auto k = sweep_kernel<T, P, XAX, MOD>;
+  hipError_t e = set_lds(k, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k, grid, dim3(64), lds, s, a);
+  return hipGetLastError();
+}
+
 template <typename T, int P>
 hipError_t launch_sweep_p(int ndesc, const SweepArgs& a, hipStream_t s) {
-  const size_t lds = size_t(a.n) * kPitch * sizeof(T);
-  dim3 grid((a.nlines + 63) / 64, ndesc);
-  if (a.xaxis) {
-    auto k = sweep_kernel<T, P, true>;
-    hipError_t e = set_lds(k, lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k, grid, dim3(64), lds, s, a);
-  } else {
-    auto k = sweep_kernel<T, P, false>;
-    hipError_t e = set_lds(k, lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k, grid, dim3(64), lds, s, a);
-  }
-  return hipGetLastError();
+  // every descriptor of one launch is either modified or shared
+  const bool mod = a.d[0].modified != 0;
+  for (int i = 1; i < ndesc; ++i)
+    if ((a.d[i].modified != 0) != mod) return hipErrorInvalidValue;
+  if (a.xaxis)
+    return mod ? launch_sweep_k<T, P, true, true>(ndesc, a, s)
+               : launch_sweep_k<T, P, true, false>(ndesc, a, s);
+  return mod ? launch_sweep_k<T, P, false, true>(ndesc, a, s)
+             : launch_sweep_k<T, P, false, false>(ndesc, a, s);
 }
 
 }  // namespace

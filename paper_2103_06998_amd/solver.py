@@ -116,6 +116,25 @@ class Solver:
         self._check(self.lib.adi_fields_device(self.h, ctypes.byref(ptr), ctypes.byref(dt)))
         return ptr.value, ("float64" if dt.value == 0 else "float32")
 
+    # -- per-kernel timing -----------------------------------------------------
+    KINDS = ("rhs_E", "rhs_H", "residual64", "sweep_x", "sweep_yz")
+
+    def profile(self, nsteps: int):
+        """Run nsteps eager steps with HIP events around every launch."""
+        self._check(self.lib.adi_profile_run(self.h, int(nsteps)))
+
+    def profile_read(self):
+        """Launches of one step with their mean durations: list of dicts."""
+        cap = 256
+        kind = (ctypes.c_int * cap)()
+        nd = (ctypes.c_int * cap)()
+        nm = (ctypes.c_int * cap)()
+        ms = (ctypes.c_float * cap)()
+        nout = ctypes.c_int()
+        self._check(self.lib.adi_profile_read(self.h, cap, ctypes.byref(nout), kind, nd, nm, ms))
+        return [dict(kind=self.KINDS[kind[i]], ncomp=nd[i], nmod=nm[i], ms=float(ms[i]))
+                for i in range(min(cap, nout.value))]
+
     # -- single stages (testing) ---------------------------------------------
     def rhs(self, stage: int, sub: int, fields, t: float = 0.0):
         nf = 6 if stage == 0 else 9
