@@ -161,6 +161,28 @@ int upload(adi_ctx* c, void* dst, const std::vector<double>& src) {
   return ADI_OK;
 }
 
+// Output planes per RHS block: the tile grid is ceil(n/32) x ceil(n/8) x
+// ceil(n/zchunk) blocks of 768 threads (one resident per CU); pick the chunk
+// (>= 8 planes, to bound the 2p-plane halo) whose block count best fills
+// whole rounds of 256 CUs.
+int pick_zchunk(int n) {
+  const long xy = long((n + 31) / 32) * ((n + 7) / 8);
+  int best = n;
+  double best_eff = -1.0;
+  for (int z = 8; z <= std::max(8, n); ++z) {
+    const long nz = (n + z - 1) / z;
+    const long blocks = xy * nz;
+    const long rounds = (blocks + 255) / 256;
+    // efficiency of the CU rounds, slightly favouring fewer halo planes
+    const double eff = double(blocks) / double(rounds * 256) * (double(z) / (z + 6.0));
+    if (eff > best_eff + 1e-9) {
+      best_eff = eff;
+      best = z;
+    }
+  }
+  return best;
+}
+
 // ---------------------------------------------------------------- enqueue
 enum LaunchKind { kKindRhsE = 0, kKindRhsH = 1, kKindResidual = 2, kKindSweepX = 3, kKindSweepYZ = 4 };
 
@@ -206,6 +228,7 @@ RhsArgs<T> rhs_args(adi_ctx* c, const void* const* f, int nf, void* const* out, 
   a.band = static_cast<const T*>(c->bandT);
   a.zw = static_cast<const T*>(c->zwT);
   a.n = c->n;
+  a.zchunk = pick_zchunk(c->n);
   a.src = c->src;
   a.tnow = c->d_t;
   a.frac_dt = (sub == 1 ? 0.25 : 0.75) * c->dt;
@@ -322,6 +345,7 @@ hipError_t enqueue_step_t(adi_ctx* c, hipStream_t s) {
         r.band = c->band64;
         r.zw = c->zw64;
         r.n = c->n;
+        r.zchunk = pick_zchunk(c->n);
         r.src = c->src;
         r.tnow = c->d_t;
         r.frac_dt = (sub == 1 ? 0.25 : 0.75) * c->dt;

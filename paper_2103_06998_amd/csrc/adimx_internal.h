@@ -58,6 +58,7 @@ struct RhsArgs {
   const T* zw;            // [op][k][2p+1]: weight of input plane k on output plane
                           // k - p + q (band entry Z[k-p+q][k], zero outside)
   int n;
+  int zchunk;             // output planes per block
   SourceArgs src;
   const double* tnow;     // device time at the start of the step
   double frac_dt;         // (1/4 or 3/4) * dt

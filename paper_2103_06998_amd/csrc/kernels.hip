@@ -113,14 +113,19 @@ __device__ __forceinline__ void static_for(F&& f) {
 
 constexpr int kTX = 32, kTY = 8, kCols = kTX * kTY;
 constexpr int kRhsThreads = 3 * kCols;  // one group of 4 waves per output component
-constexpr int kZChunk = 32;             // output planes per block
+constexpr int kPrefetch = 2;            // input planes loaded ahead of use
+
+// The residual stages keep four accumulator groups per thread; their x band
+// rows are read from LDS instead of registers to stay clear of spills.
+template <int STAGE>
+constexpr bool xband_in_lds() { return StageInfo<STAGE>::NG == 4; }
 
 template <typename TC, int P, int STAGE>
 constexpr size_t rhs_lds_bytes() {
-  constexpr int W = 2 * P + 1, HX = kTX + 2 * P, HY = kTY + 2 * P;
+  constexpr int HX = kTX + 2 * P, HY = kTY + 2 * P, W = 2 * P + 1;
   constexpr PairTab PT = make_pairs<STAGE>();
   return sizeof(TC) * (size_t(StageInfo<STAGE>::NF) * HY * HX + size_t(PT.np) * kTY * HX +
-                       4 * kTX * W + 4 * kTY * W + 4 * (kZChunk + 2 * P) * W);
+                       (xband_in_lds<STAGE>() ? 4 * kTX * W : 0));
 }
 
 // ------------------------------------------------------------ RHS kernel
@@ -128,55 +133,58 @@ constexpr size_t rhs_lds_bytes() {
 // planes; its three groups of 256 threads compute the three output
 // components.  Input planes are marched along z: each plane of every input
 // field is staged (with a p-halo in x and y) in LDS (the next plane is
-// loaded into registers while the current one is processed), the y operators
-// and then the x operators are applied in the plane, and each result is
-// scattered into a register queue of 2p+1 pending output planes with the z
-// operator's weights.  When the oldest pending plane is complete it is scaled
-// by the per-row coefficients and written.  TI: input type, TC: arithmetic
-// type, TO: output type.
+// loaded into registers while the current one is processed).  The y
+// operators are applied by one wave per (field, operator) pair, each lane
+// producing a column of kTY values from 2p + kTY staged values; the x
+// operators are applied per output column with the thread's band rows in
+// registers, and each result is scattered into a register queue of 2p+1
+// pending output planes with the z operator's weights.  When the oldest
+// pending plane is complete it is scaled by the per-row coefficients and
+// written.  TI: input type, TC: arithmetic type, TO: output type.
 template <typename TI, typename TC, typename TO, int P, int STAGE>
-__global__ __launch_bounds__(kRhsThreads) void rhs_kernel(RhsArgs<TC> a) {
-  constexpr int W = 2 * P + 1, HX = kTX + 2 * P, HY = kTY + 2 * P, ZR = kZChunk + 2 * P;
+__global__ __launch_bounds__(kRhsThreads) void rhs_kernel(RhsArgs<TC> a,
+                                                          const TC* __restrict__ band,
+                                                          const TC* __restrict__ zw) {
+  constexpr int W = 2 * P + 1, HX = kTX + 2 * P, HY = kTY + 2 * P;
   constexpr int NT = StageInfo<STAGE>::NT, NF = StageInfo<STAGE>::NF, NG = StageInfo<STAGE>::NG;
   constexpr PairTab PT = make_pairs<STAGE>();
   constexpr int NP = PT.np;
   constexpr bool kE = !(STAGE == kStageH1 || STAGE == kStageH2);
   constexpr int PLANE = NF * HY * HX;                          // staged values per plane
   constexpr int NLD = (PLANE + kRhsThreads - 1) / kRhsThreads;  // per thread
+  constexpr int NWAVES = kRhsThreads / 64;
+  static_assert(HX <= 64, "one lane per staged x column in the y pass");
 
   extern __shared__ __align__(16) unsigned char smem[];
   TC* sF = reinterpret_cast<TC*>(smem);
   TC* sG = sF + PLANE;
-  TC* sBX = sG + NP * kTY * HX;
-  TC* sBY = sBX + 4 * kTX * W;
-  TC* sZ = sBY + 4 * kTY * W;  // [op][k - (t0 - P)][q]
+  TC* sBX = sG + NP * kTY * HX;  // x band rows (residual stages only)
+  constexpr bool kXL = xband_in_lds<STAGE>();
 
   const int n = a.n;
   const size_t plane = size_t(n) * n;
   const int tid = threadIdx.x;
+  const int wave = tid / 64, lane = tid % 64;
   const int comp = tid / kCols;  // uniform per wave
   const int cid = tid % kCols, tx = cid % kTX, ty = cid / kTX;
   const int i0 = blockIdx.x * kTX, j0 = blockIdx.y * kTY;
-  const int t0 = blockIdx.z * kZChunk;
-  const int t1 = min(n, t0 + kZChunk);
-  const TC* band = a.band;
+  const int t0 = blockIdx.z * a.zchunk;
+  const int t1 = min(n, t0 + a.zchunk);
+  const int i = i0 + tx, j = j0 + ty;
 
-  for (int idx = tid; idx < 4 * kTX * W; idx += kRhsThreads) {
-    const int op = idx / (kTX * W), rem = idx % (kTX * W), r = rem / W, d = rem % W;
-    const int gi = i0 + r;
-    sBX[idx] = gi < n ? band[(size_t(op) * n + gi) * W + d] : TC(0);
-  }
-  for (int idx = tid; idx < 4 * kTY * W; idx += kRhsThreads) {
-    const int op = idx / (kTY * W), rem = idx % (kTY * W), r = rem / W, d = rem % W;
-    const int gj = j0 + r;
-    sBY[idx] = gj < n ? band[(size_t(op) * n + gj) * W + d] : TC(0);
-  }
-  // z weights of the planes this block reads: zw[(op*n + k)*W + q] is the
-  // weight of input plane k on output plane k - p + q (zero outside)
-  for (int idx = tid; idx < 4 * ZR * W; idx += kRhsThreads) {
-    const int op = idx / (ZR * W), rem = idx % (ZR * W), kk = rem / W, q = rem % W;
-    const int k = t0 - P + kk;
-    sZ[idx] = (k >= 0 && k < n) ? a.zw[(size_t(op) * n + k) * W + q] : TC(0);
+  // x band rows of this thread's output column (registers, or LDS for the
+  // residual stages)
+  TC xb[kXL ? 1 : 4][W];
+  if (kXL) {
+    for (int idx = tid; idx < 4 * kTX * W; idx += kRhsThreads) {
+      const int op = idx / (kTX * W), rem = idx % (kTX * W), r = rem / W, d = rem % W;
+      sBX[idx] = (i0 + r < n) ? band[(size_t(op) * n + i0 + r) * W + d] : TC(0);
+    }
+  } else {
+#pragma unroll
+    for (int op = 0; op < (kXL ? 1 : 4); ++op)
+#pragma unroll
+      for (int d = 0; d < W; ++d) xb[op][d] = (i < n) ? band[(size_t(op) * n + i) * W + d] : TC(0);
   }
 
   // Offsets of this thread's staged values within a plane (-1: outside the
@@ -219,31 +227,46 @@ __global__ __launch_bounds__(kRhsThreads) void rhs_kernel(RhsArgs<TC> a) {
   }
 
   const int kbeg = max(t0 - P, 0), kend = min(t1 + P, n);  // input planes to read
-  TC pre[NLD];
-  load_plane(kbeg, pre);
+  // ring of kPrefetch planes in registers: pre[0] is the next plane to stage
+  TC pre[kPrefetch][NLD];
+#pragma unroll
+  for (int b = 0; b < kPrefetch; ++b)
+    if (kbeg + b < kend) load_plane(kbeg + b, pre[b]);
   for (int k = t0 - P; k < t1 + P; ++k) {
     if (k >= kbeg && k < kend) {
       __syncthreads();  // the previous plane's passes are done with sF / sG
 #pragma unroll
       for (int u = 0; u < NLD; ++u) {
         const int idx = tid + u * kRhsThreads;
-        if (idx < PLANE) sF[idx] = pre[u];
+        if (idx < PLANE) sF[idx] = pre[0][u];
       }
-      if (k + 1 < kend) load_plane(k + 1, pre);  // in flight during this plane
+#pragma unroll
+      for (int b = 0; b + 1 < kPrefetch; ++b)
+#pragma unroll
+        for (int u = 0; u < NLD; ++u) pre[b][u] = pre[b + 1][u];
+      if (k + kPrefetch < kend) load_plane(k + kPrefetch, pre[kPrefetch - 1]);
       __syncthreads();
+      // y pass: wave w handles pairs w, w + NWAVES, ...; lane = staged x column
       static_for<NP>([&](auto pc) {
         constexpr int pr = decltype(pc)::value;
         constexpr int f = PT.field[pr], yop = PT.yop[pr];
-        for (int idx = tid; idx < kTY * HX; idx += kRhsThreads) {
-          const int yy = idx / HX, xx = idx % HX;
-          TC s = TC(0);
+        if (wave == pr % NWAVES && lane < HX) {
+          TC col[HY];
 #pragma unroll
-          for (int d = 0; d < W; ++d) s += sBY[(yop * kTY + yy) * W + d] * sF[(f * HY + yy + d) * HX + xx];
-          sG[(pr * kTY + yy) * HX + xx] = s;
+          for (int m = 0; m < HY; ++m) col[m] = sF[(f * HY + m) * HX + lane];
+#pragma unroll
+          for (int yy = 0; yy < kTY; ++yy) {
+            const int gj = min(j0 + yy, n - 1);  // rows past the patch are never written
+            const TC* yb = band + (size_t(yop) * n + gj) * W;
+            TC s = TC(0);
+#pragma unroll
+            for (int d = 0; d < W; ++d) s += yb[d] * col[yy + d];
+            sG[(pr * kTY + yy) * HX + lane] = s;
+          }
         }
       });
       __syncthreads();
-      const TC* zk = sZ + (k - (t0 - P)) * W;
+      const TC* zk = zw + size_t(k) * W;
       static_for<NT>([&](auto ic) {
         constexpr int it = decltype(ic)::value;
         constexpr Term tm = get_term<STAGE>(it);
@@ -251,16 +274,19 @@ __global__ __launch_bounds__(kRhsThreads) void rhs_kernel(RhsArgs<TC> a) {
         if (tm.out == comp) {
           TC v = TC(0);
 #pragma unroll
-          for (int d = 0; d < W; ++d) v += sBX[(tm.x * kTX + tx) * W + d] * sG[(pr * kTY + ty) * HX + tx + d];
+          for (int d = 0; d < W; ++d) {
+            const TC xw = kXL ? sBX[(tm.x * kTX + tx) * W + d] : xb[kXL ? 0 : tm.x][d];
+            v += xw * sG[(pr * kTY + ty) * HX + tx + d];
+          }
           if (tm.sign < 0) v = -v;
+          const TC* zq = zk + size_t(tm.z) * n * W;
 #pragma unroll
-          for (int q = 0; q < W; ++q) acc[tm.grp][q] += zk[tm.z * ZR * W + q] * v;
+          for (int q = 0; q < W; ++q) acc[tm.grp][q] += zq[q] * v;
         }
       });
     }
     const int te = k - P;
     if (te >= t0 && te < t1) {
-      const int i = i0 + tx, j = j0 + ty;
       if (i < n && j < n) {
         const size_t o = i + size_t(n) * j + plane * te;
         const bool bi = (i == 0 || i == n - 1), bj = (j == 0 || j == n - 1),
@@ -301,21 +327,44 @@ __global__ __launch_bounds__(kRhsThreads) void rhs_kernel(RhsArgs<TC> a) {
 // in LDS, and the tile is written back.  Lines along y and z are loaded with
 // consecutive lanes on consecutive x (coalesced); lines along x are contiguous
 // in memory and are transposed through LDS.
-constexpr int kPitch = 65;
-constexpr int kLoadCH = 32;  // rows per lane loaded together when staging
-constexpr int kCH = 16;      // rows per compute chunk
+constexpr int kLoadCH = 32;  // rows per lane loaded together
+constexpr int kCH = 8;       // rows per compute chunk of the LDS part
 
-// Factors: forward y_r = b_r - sum_k L[r][k] y_{r-1-k}; backward
-// x_r = D_r y_r - sum_k DU[r][k] x_{r+1+k} with DU = D * U (pre-scaled, so
-// every row adds one dependent FMA to the chain).  Shared factors are
-// [r*P + k] (L, DU) and [r] (D); per-line factors [((k*n) + r)*nlines + l].
+// Rows of a line kept in registers (the rest in LDS): float64 tiles would
+// limit a CU to two waves by LDS alone, so their first 72 rows stay in
+// registers; float32 tiles fit four waves per CU entirely in LDS.
+template <typename T>
+struct SweepRegRows { static constexpr int value = sizeof(T) == 8 ? 72 : 0; };
+
+__host__ __device__ constexpr int sweep_pitch(bool xax) { return xax ? 65 : 64; }
+
+// Rows of the LDS buffer: the LDS part of the lines, and for x lines also the
+// transposition of the register part.
+__host__ __device__ inline int sweep_buf_rows(int n, bool xax, int rr) {
+  const int nlds = n > rr ? n - rr : 0;
+  const int nreg = n < rr ? n : rr;
+  return xax ? (nlds > nreg ? nlds : nreg) : nlds;
+}
+
+// One wave (64 lanes) solves 64 lines, lane = line.  Rows [0, kRR) of a line
+// live in registers, rows [kRR, n) in an LDS column private to the lane.
+// Lines along y and z are read with consecutive lanes on consecutive x
+// (coalesced); lines along x are contiguous in memory and are transposed
+// through LDS (row pitch 65: conflict-free transposed access), in two parts.
+// Forward: y_r = b_r - sum_k L[r][k] y_{r-1-k}; backward:
+// x_r = D_r y_r - sum_k DU[r][k] x_{r+1+k}, DU = D * U pre-scaled, so each row
+// adds one dependent FMA.  Shared factors [r*P + k] / [r] are staged in LDS;
+// per-line factors are read as [((k*n) + r)*nlines + l].
 template <typename T, int P, bool XAX, bool MOD>
 __global__ __launch_bounds__(64) void sweep_kernel(SweepArgs a) {
+  constexpr int PIT = sweep_pitch(XAX);
+  constexpr int kRR = SweepRegRows<T>::value;
+  constexpr int kRA = kRR > 0 ? kRR : 1;  // register array extent
   extern __shared__ __align__(16) unsigned char smem[];
   T* buf = reinterpret_cast<T*>(smem);
-  T* sfac = buf + size_t(a.n) * kPitch;  // shared factors: L[n*P], DU[n*P], D[n]
-  const SweepDesc& ds = a.d[blockIdx.y];
   const int n = a.n, nl = a.nlines, lane = threadIdx.x;
+  T* sfac = buf + size_t(sweep_buf_rows(n, XAX, kRR)) * PIT;  // shared: L[n*P], DU[n*P], D[n]
+  const SweepDesc& ds = a.d[blockIdx.y];
   const int l0 = blockIdx.x * 64, l = l0 + lane;
   const bool act = l < nl;
   const int nll = min(64, nl - l0);  // lines in this tile
@@ -326,6 +375,7 @@ __global__ __launch_bounds__(64) void sweep_kernel(SweepArgs a) {
   const int lc = act ? l : 0;
   const size_t lbase = (ds.axis == 1) ? size_t(lc % n) + size_t(lc / n) * n2 : size_t(lc);
   const size_t rstride = (ds.axis == 1) ? size_t(n) : n2;
+  const int nreg = min(n, kRR);
 
   if (!MOD) {
     const T* Lf = static_cast<const T*>(ds.L);
@@ -338,40 +388,84 @@ __global__ __launch_bounds__(64) void sweep_kernel(SweepArgs a) {
     for (int i = lane; i < n; i += 64) sfac[2 * n * P + i] = Df[i];
   }
 
-  // ---- stage the 64 x n tile in LDS: buf[r * kPitch + line]
-  if (XAX) {
-    // the tile is nll * n contiguous values; lane reads elements e0 + c*64 + lane
-    const int total = nll * n;
+  // x lines: copy columns [c0, c1) of the nll contiguous lines into
+  // buf[(r - c0) * PIT + line] (coalesced global reads)
+  const float inv_w = 1.0f;  // placeholder to keep the lambda signature simple
+  (void)inv_w;
+  auto stage_cols = [&](int c0, int c1) {
+    const int wdt = c1 - c0, total = nll * wdt;
+    const float inv = 1.0f / float(wdt);
     const T* src = in + size_t(l0) * n;
-    const float inv_n = 1.0f / float(n);
     for (int e0 = 0; e0 < total; e0 += 64 * kLoadCH) {
       T v[kLoadCH];
 #pragma unroll
       for (int c = 0; c < kLoadCH; ++c) {
         const int e = min(e0 + c * 64 + lane, total - 1);
-        v[c] = src[e];
+        int ll = int((float(e) + 0.5f) * inv);
+        int r = e - ll * wdt;
+        if (r < 0) { --ll; r += wdt; }
+        if (r >= wdt) { ++ll; r -= wdt; }
+        v[c] = src[size_t(ll) * n + c0 + r];
       }
 #pragma unroll
       for (int c = 0; c < kLoadCH; ++c) {
         const int e = e0 + c * 64 + lane;
-        int ll = int((float(e) + 0.5f) * inv_n);
-        int r = e - ll * n;
-        if (r < 0) { --ll; r += n; }
-        if (r >= n) { ++ll; r -= n; }
-        if (e < total) buf[r * kPitch + ll] = v[c];
+        int ll = int((float(e) + 0.5f) * inv);
+        int r = e - ll * wdt;
+        if (r < 0) { --ll; r += wdt; }
+        if (r >= wdt) { ++ll; r -= wdt; }
+        if (e < total) buf[r * PIT + ll] = v[c];
       }
     }
+  };
+  auto unstage_cols = [&](int c0, int c1) {
+    const int wdt = c1 - c0, total = nll * wdt;
+    const float inv = 1.0f / float(wdt);
+    T* dst = out + size_t(l0) * n;
+    const T* ac = accp ? accp + size_t(l0) * n : nullptr;
+    for (int e0 = 0; e0 < total; e0 += 64 * kLoadCH) {
+#pragma unroll
+      for (int c = 0; c < kLoadCH; ++c) {
+        const int e = e0 + c * 64 + lane;
+        int ll = int((float(e) + 0.5f) * inv);
+        int r = e - ll * wdt;
+        if (r < 0) { --ll; r += wdt; }
+        if (r >= wdt) { ++ll; r -= wdt; }
+        if (e < total) {
+          const size_t o = size_t(ll) * n + c0 + r;
+          T v = buf[r * PIT + ll];
+          if (ac) v += ac[o];
+          dst[o] = v;
+        }
+      }
+    }
+  };
+
+  // ---- load: registers for rows [0, nreg), LDS for rows [kRR, n)
+  T yr[kRA];
+  if (XAX) {
+    if (kRR > 0) {
+      stage_cols(0, nreg);
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < kRR; ++r) yr[r] = (r < nreg) ? buf[r * PIT + lane] : T(0);
+      __syncthreads();
+    }
+    if (n > kRR) stage_cols(kRR, n);
+    __syncthreads();
   } else {
-    for (int r0 = 0; r0 < n; r0 += kLoadCH) {
+#pragma unroll
+    for (int r = 0; r < kRR; ++r) yr[r] = in[lbase + size_t(min(r, n - 1)) * rstride];
+    for (int r0 = kRR; r0 < n; r0 += kLoadCH) {
       T v[kLoadCH];
 #pragma unroll
       for (int c = 0; c < kLoadCH; ++c) v[c] = in[lbase + size_t(min(r0 + c, n - 1)) * rstride];
 #pragma unroll
       for (int c = 0; c < kLoadCH; ++c)
-        if (r0 + c < n) buf[(r0 + c) * kPitch + lane] = v[c];
+        if (r0 + c < n) buf[(r0 + c - kRR) * PIT + lane] = v[c];
     }
+    __syncthreads();  // shared factors
   }
-  __syncthreads();
 
   const size_t fstride = size_t(n) * nl;
   const T* __restrict__ Lm = static_cast<const T*>(ds.L);
@@ -390,122 +484,115 @@ __global__ __launch_bounds__(64) void sweep_kernel(SweepArgs a) {
     return sfac[2 * n * P + r];
   };
 
-  {
-    // ---- forward substitution in chunks of kCH rows (rows >= n are padding:
-    // their factors are read from row n-1 and their results are dropped)
-    T h[P];
+  T h[P];
 #pragma unroll
-    for (int k = 0; k < P; ++k) h[k] = T(0);
-    T fa[kCH][P];
+  for (int k = 0; k < P; ++k) h[k] = T(0);
+  // ---- forward, register rows (rows >= n are padding and never stored)
 #pragma unroll
-    for (int c = 0; c < kCH; ++c)
+  for (int r = 0; r < kRR; ++r) {
+    const int rf = min(r, n - 1);
+    T s = yr[r];
 #pragma unroll
-      for (int k = 0; k < P; ++k) fa[c][k] = fL(min(c, n - 1), k);
-    for (int r0 = 0; r0 < n; r0 += kCH) {
-      T v[kCH], fb[kCH][P];
+    for (int k = P - 1; k >= 0; --k) s -= fL(rf, k) * h[k];
 #pragma unroll
-      for (int c = 0; c < kCH; ++c) v[c] = buf[min(r0 + c, n - 1) * kPitch + lane];
-#pragma unroll
-      for (int c = 0; c < kCH; ++c)
-#pragma unroll
-        for (int k = 0; k < P; ++k) fb[c][k] = fL(min(r0 + kCH + c, n - 1), k);
-#pragma unroll
-      for (int c = 0; c < kCH; ++c) {
-        T s = v[c];
-#pragma unroll
-        for (int k = P - 1; k >= 0; --k) s -= fa[c][k] * h[k];
-#pragma unroll
-        for (int k = P - 1; k > 0; --k) h[k] = h[k - 1];
-        h[0] = s;
-        v[c] = s;
-      }
-#pragma unroll
-      for (int c = 0; c < kCH; ++c)
-        if (r0 + c < n) buf[(r0 + c) * kPitch + lane] = v[c];
-#pragma unroll
-      for (int c = 0; c < kCH; ++c)
-#pragma unroll
-        for (int k = 0; k < P; ++k) fa[c][k] = fb[c][k];
-    }
-
-    // ---- backward substitution in chunks of kCH rows from the end
-#pragma unroll
-    for (int k = 0; k < P; ++k) h[k] = T(0);
-    T da[kCH];
+    for (int k = P - 1; k > 0; --k) h[k] = h[k - 1];
+    h[0] = s;
+    yr[r] = s;
+  }
+  // ---- forward, LDS rows
+  for (int r0 = kRR; r0 < n; r0 += kCH) {
+    T v[kCH], f[kCH][P];
 #pragma unroll
     for (int c = 0; c < kCH; ++c) {
-      const int r = max(n - 1 - c, 0);
+      const int rf = min(r0 + c, n - 1);
+      v[c] = buf[(rf - kRR) * PIT + lane];
 #pragma unroll
-      for (int k = 0; k < P; ++k) fa[c][k] = fU(r, k);
-      da[c] = fD(r);
+      for (int k = 0; k < P; ++k) f[c][k] = fL(rf, k);
     }
-    for (int r0 = n - 1; r0 >= 0; r0 -= kCH) {
-      T v[kCH], fb[kCH][P], db[kCH];
 #pragma unroll
-      for (int c = 0; c < kCH; ++c) v[c] = buf[max(r0 - c, 0) * kPitch + lane];
+    for (int c = 0; c < kCH; ++c) {
+      T s = v[c];
 #pragma unroll
-      for (int c = 0; c < kCH; ++c) {
-        const int r = max(r0 - kCH - c, 0);
+      for (int k = P - 1; k >= 0; --k) s -= f[c][k] * h[k];
 #pragma unroll
-        for (int k = 0; k < P; ++k) fb[c][k] = fU(r, k);
-        db[c] = fD(r);
-      }
+      for (int k = P - 1; k > 0; --k) h[k] = h[k - 1];
+      h[0] = s;
+      v[c] = s;
+    }
 #pragma unroll
-      for (int c = 0; c < kCH; ++c) {
-        T s = da[c] * v[c];
+    for (int c = 0; c < kCH; ++c)
+      if (r0 + c < n) buf[(r0 + c - kRR) * PIT + lane] = v[c];
+  }
+  // ---- backward, LDS rows (from the last row down to kRR)
 #pragma unroll
-        for (int k = P - 1; k >= 0; --k) s -= fa[c][k] * h[k];
+  for (int k = 0; k < P; ++k) h[k] = T(0);
+  for (int r0 = n - 1; r0 >= kRR; r0 -= kCH) {
+    T v[kCH], f[kCH][P], d[kCH];
+#pragma unroll
+    for (int c = 0; c < kCH; ++c) {
+      const int rf = max(r0 - c, kRR);
+      v[c] = buf[(rf - kRR) * PIT + lane];
+#pragma unroll
+      for (int k = 0; k < P; ++k) f[c][k] = fU(rf, k);
+      d[c] = fD(rf);
+    }
+#pragma unroll
+    for (int c = 0; c < kCH; ++c) {
+      if (r0 - c >= kRR) {  // uniform
+        T s = d[c] * v[c];
+#pragma unroll
+        for (int k = P - 1; k >= 0; --k) s -= f[c][k] * h[k];
 #pragma unroll
         for (int k = P - 1; k > 0; --k) h[k] = h[k - 1];
         h[0] = s;
         v[c] = s;
       }
+    }
 #pragma unroll
-      for (int c = 0; c < kCH; ++c)
-        if (r0 - c >= 0) buf[(r0 - c) * kPitch + lane] = v[c];
+    for (int c = 0; c < kCH; ++c)
+      if (r0 - c >= kRR) buf[(r0 - c - kRR) * PIT + lane] = v[c];
+  }
+  // ---- backward, register rows (padding rows r >= n are skipped)
 #pragma unroll
-      for (int c = 0; c < kCH; ++c) {
+  for (int r = kRR - 1; r >= 0; --r) {
+    if (r < n) {  // uniform
+      T s = fD(r) * yr[r];
 #pragma unroll
-        for (int k = 0; k < P; ++k) fa[c][k] = fb[c][k];
-        da[c] = db[c];
-      }
+      for (int k = P - 1; k >= 0; --k) s -= fU(r, k) * h[k];
+#pragma unroll
+      for (int k = P - 1; k > 0; --k) h[k] = h[k - 1];
+      h[0] = s;
+      yr[r] = s;
     }
   }
-  __syncthreads();
 
-  // ---- write the tile back
+  // ---- store
   if (XAX) {
-    const int total = nll * n;
-    T* dst = out + size_t(l0) * n;
-    const T* ac = accp ? accp + size_t(l0) * n : nullptr;
-    const float inv_n = 1.0f / float(n);
-    for (int e0 = 0; e0 < total; e0 += 64 * kLoadCH) {
+    __syncthreads();
+    if (n > kRR) unstage_cols(kRR, n);
+    if (kRR > 0) {
+      __syncthreads();
 #pragma unroll
-      for (int c = 0; c < kLoadCH; ++c) {
-        const int e = e0 + c * 64 + lane;
-        int ll = int((float(e) + 0.5f) * inv_n);
-        int r = e - ll * n;
-        if (r < 0) { --ll; r += n; }
-        if (r >= n) { ++ll; r -= n; }
-        if (e < total) {
-          T v = buf[r * kPitch + ll];
-          if (ac) v += ac[e];
-          dst[e] = v;
-        }
-      }
+      for (int r = 0; r < kRR; ++r)
+        if (r < nreg) buf[r * PIT + lane] = yr[r];
+      __syncthreads();
+      unstage_cols(0, nreg);
     }
   } else if (act) {
-    for (int r0 = 0; r0 < n; r0 += kLoadCH) {
 #pragma unroll
-      for (int c = 0; c < kLoadCH; ++c) {
-        const int r = r0 + c;
-        if (r < n) {
-          const size_t o = lbase + size_t(r) * rstride;
-          T v = buf[r * kPitch + lane];
-          if (accp) v += accp[o];
-          out[o] = v;
-        }
+    for (int r = 0; r < kRR; ++r) {
+      if (r < n) {
+        const size_t o = lbase + size_t(r) * rstride;
+        T v = yr[r];
+        if (accp) v += accp[o];
+        out[o] = v;
       }
+    }
+    for (int r = kRR; r < n; ++r) {
+      const size_t o = lbase + size_t(r) * rstride;
+      T v = buf[(r - kRR) * PIT + lane];
+      if (accp) v += accp[o];
+      out[o] = v;
     }
   }
   if (a.tick_t && blockIdx.x == 0 && blockIdx.y == 0 && lane == 0) *a.tick_t += a.tick_dt;
@@ -610,8 +697,8 @@ hipError_t launch_rhs_t(const RhsArgs<TC>& a, hipStream_t s) {
   hipError_t e = set_lds(k, lds);
   if (e != hipSuccess) return e;
   const int n = a.n;
-  dim3 grid((n + kTX - 1) / kTX, (n + kTY - 1) / kTY, (n + kZChunk - 1) / kZChunk);
-  hipLaunchKernelGGL(k, grid, dim3(kRhsThreads), lds, s, a);
+  dim3 grid((n + kTX - 1) / kTX, (n + kTY - 1) / kTY, (n + a.zchunk - 1) / a.zchunk);
+  hipLaunchKernelGGL(k, grid, dim3(kRhsThreads), lds, s, a, a.band, a.zw);
   return hipGetLastError();
 }
 
@@ -648,7 +735,8 @@ hipError_t launch_rhs_any(int stage, int p, const RhsArgs<TC>& a, hipStream_t s)
 
 template <typename T, int P, bool XAX, bool MOD>
 hipError_t launch_sweep_k(int ndesc, const SweepArgs& a, hipStream_t s) {
-  const size_t lds = (size_t(a.n) * kPitch + (MOD ? 0 : size_t(a.n) * (2 * P + 1))) * sizeof(T);
+  const size_t lds = (size_t(sweep_buf_rows(a.n, XAX, SweepRegRows<T>::value)) * sweep_pitch(XAX) +
+                      (MOD ? 0 : size_t(a.n) * (2 * P + 1))) * sizeof(T);
   dim3 grid((a.nlines + 63) / 64, ndesc);
   auto k = sweep_kernel<T, P, XAX, MOD>;
   hipError_t e = set_lds(k, lds);
