@@ -34,6 +34,7 @@ extern "C" {
 #endif
 
 typedef struct adi_ctx adi_ctx;
+typedef struct adi_nn adi_nn;
 
 enum {
   ADI_OK = 0,
@@ -163,6 +164,82 @@ void adi_destroy(adi_ctx* ctx);
  */
 int adi_rhs(adi_ctx* ctx, int stage, int sub, const double* in, double t, double* out);
 int adi_solve(adi_ctx* ctx, int stage, int sub, double* inout);
+
+/* ===================================================================== *
+ * Learned closure.  Not part of the paper's method: a small network that
+ * corrects the splitting error of a coarse ADI step so that larger steps
+ * keep the accuracy of smaller ones.  The network is three 3x3x3
+ * convolutions with zero padding on the n x n x n coefficient grid,
+ * channels last ([z][y][x][c], x fastest): cin -> 32 (SiLU) -> 32 (SiLU) ->
+ * cout.  Operands are bfloat16, accumulation float32 (MFMA); the float32
+ * master parameters live on the device.
+ *
+ * Parameter vector (float32, adi_nn_param_count entries), per layer l in
+ * order: W_l[t][ci][co] (27 x cin_l x cout_l, tap t = 9 tz + 3 ty + tx, the
+ * input voxel at offset (tz-1, ty-1, tx-1) from the output voxel), then b_l.
+ *
+ * The network handle has its own device memory; its calls run on the
+ * hip_stream given at creation.  All _dev pointers are device memory owned
+ * by the caller.
+ * ===================================================================== */
+
+/* Create a network with cin (1..16) inputs, chid (= 32) hidden channels and
+ * cout (1..16) outputs; parameters start at zero. */
+int adi_nn_create(adi_nn** out, int cin, int chid, int cout, void* hip_stream);
+int adi_nn_param_count(const adi_nn* nn);
+/* Upload all parameters (host float32, layout above; finite) and reset the
+ * Adam moments. */
+int adi_nn_set_params(adi_nn* nn, const float* params);
+int adi_nn_get_params(adi_nn* nn, float* params_out);
+/* y_dev[v][cout] = net(x_dev[v][cin]) on an nx x ny x nz grid (float32);
+ * keeps the activations for adi_nn_backward. */
+int adi_nn_forward(adi_nn* nn, const float* x_dev, float* y_dev, int nx, int ny, int nz);
+/* Parameter gradients of the loss whose gradient w.r.t. the last forward's
+ * output is dy_dev[v][cout]; they replace the previous gradients. */
+int adi_nn_backward(adi_nn* nn, const float* dy_dev);
+int adi_nn_get_grads(adi_nn* nn, float* grads_out);
+/* One Adam step (bias-corrected, step number t >= 1) on the gradients. */
+int adi_nn_adam(adi_nn* nn, float lr, float beta1, float beta2, float eps, int t);
+/* Mean squared error of y against target over count entries: writes
+ * dy_dev = 2 (y - target) / count and, if loss is not NULL, waits and
+ * stores the loss. */
+int adi_nn_mse(adi_nn* nn, const float* y_dev, const float* target_dev, size_t count,
+               float* dy_dev, double* loss);
+const char* adi_nn_last_error(const adi_nn* nn);
+void adi_nn_destroy(adi_nn* nn);
+
+/*
+ * Solver side of the closure (contexts must be factored).  With S the state
+ * before a coarse step and C the state after it, s = RMS of C over all 6 n^3
+ * values:
+ *   features x[v][0..5]   = C_c[v] / s,
+ *            x[v][6..11]  = (C_c[v] - S_c[v]) / s,
+ *            x[v][12..14] = log eps, log mu, c/(1+c) with c = sigma dt/(4 eps),
+ *            x[v][15]     = B(v) (dt/2) amp (g(t - 3dt/4) + g(t - dt/4)) / s, the
+ *                           dipole's impulse over the step (t = time after
+ *                           it, g its time profile) times the tensor-product
+ *                           basis value B(v) of coefficient v at the dipole;
+ *   target   t[v][c] = (F_c[v] - C_c[v]) / s with F a finer solution;
+ *   apply    C_c[v] += s y[v][c] except on the PEC-constrained coefficients.
+ * adi_copy_state copies the state and time of src into dst (same n; float32
+ * and float64 states convert).  adi_closure_mark stores the current state
+ * as S.  scale_dev holds one float.
+ */
+int adi_copy_state(adi_ctx* dst, const adi_ctx* src);
+int adi_closure_mark(adi_ctx* ctx);
+int adi_closure_features(adi_ctx* ctx, float* x_dev, float* scale_dev);
+int adi_closure_target(adi_ctx* fine, adi_ctx* coarse, const float* scale_dev, float* t_dev);
+int adi_closure_apply(adi_ctx* ctx, const float* y_dev, const float* scale_dev);
+/*
+ * nsteps closure steps on the context's stream: mark, one ADI step, features,
+ * network forward, apply.  nn must map 16 features to 6 outputs and must not
+ * be used on another stream meanwhile.  gate > 0 skips a correction whose
+ * RMS (in units of s) exceeds gate -- that step stays a plain
+ * ADI step -- and counts it (adi_closure_rejected, which waits); gate <= 0
+ * applies every one.
+ */
+int adi_step_closure(adi_ctx* ctx, adi_nn* nn, int nsteps, float gate);
+int adi_closure_rejected(adi_ctx* ctx, int* count);
 
 #ifdef __cplusplus
 }

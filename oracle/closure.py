@@ -122,3 +122,61 @@ def bf16_round(a: np.ndarray) -> np.ndarray:
     lsb = (u >> 16) & 1
     u = (u + 0x7FFF + lsb) & 0xFFFF0000
     return u.view(np.float32).astype(np.float64)
+
+
+# --------------------------------------------------------------------------
+# Solver-side glue of the closure (plain definitions, float64).  States are
+# (6, n, n, n) arrays [E1, E2, E3, H1, H2, H3] in [z][y][x] order; network
+# tensors are channels last.
+# --------------------------------------------------------------------------
+N_FEATURES = 16
+
+
+def closure_scale(C: np.ndarray) -> float:
+    """RMS of a state over all its 6 n^3 values."""
+    return float(np.sqrt(np.mean(C * C)))
+
+
+def closure_features(problem, C: np.ndarray, S: np.ndarray, t_after: float):
+    """Network inputs of one coarse step from S (before) to C (after).
+
+    Channels: C / s (6), (C - S) / s (6), log eps, log mu, c / (1 + c) with
+    the conductivity number c = sigma dt / (4 eps), and the dipole's impulse
+    over the step, dt/2 (J(t - 3dt/4) + J(t - dt/4)) with J the source's
+    coefficient field (the substep midpoints of the scheme), divided by s.
+    Returns (x, s).
+    """
+    from . import maxwell
+
+    n, dt = problem.n, problem.dt
+    s = closure_scale(C)
+    x = np.zeros((n, n, n, N_FEATURES))
+    for c in range(6):
+        x[..., c] = C[c] / s
+        x[..., 6 + c] = (C[c] - S[c]) / s
+    cc = problem.sig * dt / (4.0 * problem.eps)
+    x[..., 12] = np.log(problem.eps)
+    x[..., 13] = np.log(problem.mu)
+    x[..., 14] = cc / (1.0 + cc)
+    src = problem.source
+    if src is not None and src.amp != 0.0:
+        J = problem.source_rows(src.comp, t_after - 0.75 * dt) + \
+            problem.source_rows(src.comp, t_after - 0.25 * dt)
+        x[..., 15] = 0.5 * dt * J / s
+    return x, s
+
+
+def closure_target(F: np.ndarray, C: np.ndarray, s: float) -> np.ndarray:
+    """(F - C) / s channels last: the correction the network learns."""
+    return np.moveaxis((F - C) / s, 0, -1)
+
+
+def closure_apply(C: np.ndarray, y: np.ndarray, s: float) -> np.ndarray:
+    """C + s y on every coefficient that the PEC condition leaves free."""
+    from . import maxwell
+
+    out = C.copy()
+    for c in range(6):
+        kind, comp = ("E", c) if c < 3 else ("H", c - 3)
+        out[c] += maxwell.zero_boundary(s * y[..., c], maxwell.dirichlet_axes(kind, comp))
+    return out

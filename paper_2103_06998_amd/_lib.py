@@ -23,6 +23,7 @@ STATUS_NAMES = {0: "ADI_OK", -1: "ADI_EINVAL", -2: "ADI_ENOMEM", -3: "ADI_EHIP",
 _P = ctypes.c_void_p
 _D = ctypes.POINTER(ctypes.c_double)
 _I = ctypes.c_int
+_F = ctypes.POINTER(ctypes.c_float)
 SIGNATURES = {
     "adi_create": (_I, [ctypes.POINTER(_P), _I, _I, _I, _I, _I, _P]),
     "adi_ncoef": (_I, [_P]),
@@ -46,6 +47,25 @@ SIGNATURES = {
     "adi_profile_read": (_I, [_P, _I, ctypes.POINTER(_I), ctypes.POINTER(_I),
                               ctypes.POINTER(_I), ctypes.POINTER(_I),
                               ctypes.POINTER(ctypes.c_float)]),
+    # learned closure
+    "adi_nn_create": (_I, [ctypes.POINTER(_P), _I, _I, _I, _P]),
+    "adi_nn_param_count": (_I, [_P]),
+    "adi_nn_set_params": (_I, [_P, _F]),
+    "adi_nn_get_params": (_I, [_P, _F]),
+    "adi_nn_forward": (_I, [_P, _P, _P, _I, _I, _I]),
+    "adi_nn_backward": (_I, [_P, _P]),
+    "adi_nn_get_grads": (_I, [_P, _F]),
+    "adi_nn_adam": (_I, [_P, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, _I]),
+    "adi_nn_mse": (_I, [_P, _P, _P, ctypes.c_size_t, _P, _D]),
+    "adi_nn_last_error": (ctypes.c_char_p, [_P]),
+    "adi_nn_destroy": (None, [_P]),
+    "adi_copy_state": (_I, [_P, _P]),
+    "adi_closure_mark": (_I, [_P]),
+    "adi_closure_features": (_I, [_P, _P, _P]),
+    "adi_closure_target": (_I, [_P, _P, _P, _P]),
+    "adi_closure_apply": (_I, [_P, _P, _P]),
+    "adi_step_closure": (_I, [_P, _P, _I, ctypes.c_float]),
+    "adi_closure_rejected": (_I, [_P, ctypes.POINTER(_I)]),
 }
 
 _lib = None

@@ -21,11 +21,11 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           # packed FP32 instructions are disabled for all device code
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-I", os.path.join(ROOT, "include"), "-I", CSRC]
-SOURCES = ["kernels.hip", "adimx.cpp", "host_basis.cpp"]
+SOURCES = ["kernels.hip", "adimx.cpp", "host_basis.cpp", "closure.hip", "closure.cpp"]
 
 
 def _compile(src: str) -> str:
-    obj = os.path.join(OBJDIR, os.path.splitext(src)[0] + ".o")
+    obj = os.path.join(OBJDIR, src.replace(".", "_") + ".o")
     cmd = [HIPCC] + COMMON + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:

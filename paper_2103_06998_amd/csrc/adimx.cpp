@@ -12,6 +12,7 @@
 // the float32 solve and one correction solve.
 #include "adimx.h"
 #include "adimx_internal.h"
+#include "closure_internal.h"
 
 #include <algorithm>
 #include <cmath>
@@ -85,6 +86,14 @@ struct adi_ctx {
   std::vector<double> launch_ms_sum;
   int profiled_steps = 0;
   size_t launch_idx = 0;
+
+  // learned closure (allocated on first use)
+  void* cl_prev = nullptr;      // state before the last coarse step (6 D, field type)
+  float* cl_mat = nullptr;      // material features [D][3]
+  float* cl_red = nullptr;      // reduction partials [kClosureBlocks], scale [1]
+  int* cl_flag = nullptr;       // [0] gate flag, [1] rejected-correction counter
+  bool cl_mat_valid = false;    // cl_mat matches the last factorisation
+  bool cl_marked = false;       // cl_prev holds a state
 
   bool refine() const { return prec == ADI_FP32_REFINE; }
 };
@@ -593,6 +602,7 @@ int adi_factor(adi_ctx* c, double dt) {
   const int n = c->n, p = c->p, W = 2 * p + 1;
   const size_t D = c->D;
   c->dt = dt;
+  c->cl_mat_valid = false;
 
   // 1D operators (float64, exact Gauss quadrature)
   Gram1D g = build_gram(c->N, p);
@@ -813,6 +823,10 @@ void adi_destroy(adi_ctx* c) {
   drop_graph(c);
   for (hipEvent_t e : c->events) hipEventDestroy(e);
   if (c->own_ws && c->ws) hipFree(c->ws);
+  if (c->cl_prev) hipFree(c->cl_prev);
+  if (c->cl_mat) hipFree(c->cl_mat);
+  if (c->cl_red) hipFree(c->cl_red);
+  if (c->cl_flag) hipFree(c->cl_flag);
   if (c->cap) hipStreamDestroy(c->cap);
   delete c;
 }
@@ -880,6 +894,180 @@ int adi_solve(adi_ctx* c, int stage, int sub, double* inout) {
   } while (false);
   hipFree(d);
   return st;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------ closure glue
+namespace {
+
+constexpr int kClosureBlocks = 1024;
+
+int closure_ready(adi_ctx* c) {
+  if (!c->factored) return fail(c, ADI_ESTATE, "adi_factor first");
+  const size_t D = c->D;
+  if (!c->cl_prev) {
+    void* p = nullptr;
+    HIPCHK(c, hipMalloc(&p, 6 * D * c->esz));
+    c->cl_prev = p;
+    HIPCHK(c, hipMalloc(reinterpret_cast<void**>(&c->cl_mat), D * 3 * sizeof(float)));
+    HIPCHK(c, hipMalloc(reinterpret_cast<void**>(&c->cl_red), (kClosureBlocks + 64) * sizeof(float)));
+    HIPCHK(c, hipMalloc(reinterpret_cast<void**>(&c->cl_flag), 64 * sizeof(int)));
+    HIPCHK(c, hipMemset(c->cl_flag, 0, 64 * sizeof(int)));
+  }
+  if (!c->cl_mat_valid) {
+    // per-coefficient material features: log eps, log mu, c / (1 + c) with
+    // the conductivity number c = sigma dt / (4 eps) of the trapezoidal rule
+    std::vector<float> f(D * 3);
+    for (size_t i = 0; i < D; ++i) {
+      const double cc = c->sig[i] * c->dt / (4.0 * c->eps[i]);
+      f[i * 3 + 0] = float(std::log(c->eps[i]));
+      f[i * 3 + 1] = float(std::log(c->mu[i]));
+      f[i * 3 + 2] = float(cc / (1.0 + cc));
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(c->cl_mat, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice));
+    c->cl_mat_valid = true;
+  }
+  return ADI_OK;
+}
+
+float* cl_scale(adi_ctx* c) { return c->cl_red + kClosureBlocks; }
+
+hipError_t enqueue_mark(adi_ctx* c) {
+  return hipMemcpyAsync(c->cl_prev, c->B[0], 6 * c->D * c->esz, hipMemcpyDeviceToDevice, c->stream);
+}
+
+// scale = RMS of the state; x = features of (state, cl_prev, material, source)
+hipError_t enqueue_features(adi_ctx* c, float* x, float* scale) {
+  hipError_t e;
+  if (c->esz == 8) {
+    const double* st = static_cast<const double*>(c->B[0]);
+    e = nn::launch_state_scale<double>(st, 6 * c->D, c->cl_red, kClosureBlocks, scale, c->stream);
+    if (e == hipSuccess)
+      e = nn::launch_features<double>(st, static_cast<const double*>(c->cl_prev), c->cl_mat, c->n,
+                                      scale, c->src, c->d_t, c->dt, x, c->stream);
+  } else {
+    const float* st = static_cast<const float*>(c->B[0]);
+    e = nn::launch_state_scale<float>(st, 6 * c->D, c->cl_red, kClosureBlocks, scale, c->stream);
+    if (e == hipSuccess)
+      e = nn::launch_features<float>(st, static_cast<const float*>(c->cl_prev), c->cl_mat, c->n,
+                                     scale, c->src, c->d_t, c->dt, x, c->stream);
+  }
+  return e;
+}
+
+hipError_t enqueue_apply(adi_ctx* c, const float* y, const float* scale, const int* flag) {
+  if (c->esz == 8)
+    return nn::launch_apply<double>(static_cast<double*>(c->B[0]), c->n, y, scale, flag, c->stream);
+  return nn::launch_apply<float>(static_cast<float*>(c->B[0]), c->n, y, scale, flag, c->stream);
+}
+
+}  // namespace
+
+extern "C" {
+
+int adi_copy_state(adi_ctx* dst, const adi_ctx* src) {
+  if (!dst || !src) return ADI_EINVAL;
+  if (dst->n != src->n) return fail(dst, ADI_EINVAL, "grids differ");
+  if (!src->ws) return fail(dst, ADI_ESTATE, "source has no state");
+  if (!dst->ws) {
+    int st = ensure_workspace(dst);
+    if (st != ADI_OK) return st;
+  }
+  if (src->stream != dst->stream) HIPCHK(dst, hipStreamSynchronize(src->stream));
+  const size_t count = 6 * dst->D;
+  if (dst->esz == src->esz) {
+    HIPCHK(dst, hipMemcpyAsync(dst->B[0], src->B[0], count * dst->esz, hipMemcpyDeviceToDevice,
+                               dst->stream));
+  } else {
+    HIPCHK(dst, launch_convert<float>(src->B[0], dst->B[0], count, src->esz == 8 ? 0 : 1,
+                                      dst->stream));
+  }
+  HIPCHK(dst, hipMemcpyAsync(dst->d_t, src->d_t, 8, hipMemcpyDeviceToDevice, dst->stream));
+  dst->t = src->t;
+  return ADI_OK;
+}
+
+int adi_closure_mark(adi_ctx* c) {
+  if (!c) return ADI_EINVAL;
+  int st = closure_ready(c);
+  if (st != ADI_OK) return st;
+  HIPCHK(c, enqueue_mark(c));
+  c->cl_marked = true;
+  return ADI_OK;
+}
+
+int adi_closure_features(adi_ctx* c, float* x_dev, float* scale_dev) {
+  if (!c || !x_dev || !scale_dev) return ADI_EINVAL;
+  int st = closure_ready(c);
+  if (st != ADI_OK) return st;
+  if (!c->cl_marked) return fail(c, ADI_ESTATE, "adi_closure_mark first");
+  HIPCHK(c, enqueue_features(c, x_dev, scale_dev));
+  return ADI_OK;
+}
+
+int adi_closure_target(adi_ctx* fine, adi_ctx* coarse, const float* scale_dev, float* t_dev) {
+  if (!fine || !coarse || !scale_dev || !t_dev) return ADI_EINVAL;
+  if (fine->n != coarse->n || !fine->ws || !coarse->ws)
+    return fail(coarse, ADI_EINVAL, "grids differ or no state");
+  if (fine->esz != coarse->esz) return fail(coarse, ADI_EINVAL, "precisions differ");
+  if (fine->stream != coarse->stream) HIPCHK(coarse, hipStreamSynchronize(fine->stream));
+  if (coarse->esz == 8)
+    HIPCHK(coarse, nn::launch_target<double>(static_cast<const double*>(fine->B[0]),
+                                             static_cast<const double*>(coarse->B[0]), coarse->D,
+                                             scale_dev, t_dev, coarse->stream));
+  else
+    HIPCHK(coarse, nn::launch_target<float>(static_cast<const float*>(fine->B[0]),
+                                            static_cast<const float*>(coarse->B[0]), coarse->D,
+                                            scale_dev, t_dev, coarse->stream));
+  return ADI_OK;
+}
+
+int adi_closure_apply(adi_ctx* c, const float* y_dev, const float* scale_dev) {
+  if (!c || !y_dev || !scale_dev) return ADI_EINVAL;
+  if (!c->ws) return fail(c, ADI_ESTATE, "no state");
+  HIPCHK(c, enqueue_apply(c, y_dev, scale_dev, nullptr));
+  return ADI_OK;
+}
+
+int adi_step_closure(adi_ctx* c, adi_nn* nn_, int nsteps, float gate) {
+  if (!c || !nn_ || nsteps < 0) return ADI_EINVAL;
+  if (!c->factored || !c->exec) return fail(c, ADI_ESTATE, "adi_factor must succeed first");
+  if (nn::closure_cin(nn_) != nn::kFeatures || nn::closure_cout(nn_) != nn::kOutputs)
+    return fail(c, ADI_EINVAL, "network must map 16 features to 6 corrections");
+  int st = closure_ready(c);
+  if (st != ADI_OK) return st;
+  const int n = c->n;
+  float *x = nullptr, *y = nullptr, *scale = nullptr, *partial = nullptr;
+  st = nn::closure_buffers(nn_, n, n, n, &x, &y, &scale, &partial);
+  if (st != ADI_OK) return fail(c, st, "network buffers");
+  for (int i = 0; i < nsteps; ++i) {
+    HIPCHK(c, enqueue_mark(c));
+    HIPCHK(c, hipGraphLaunch(c->exec, c->stream));
+    HIPCHK(c, enqueue_features(c, x, scale));
+    st = nn::closure_forward(nn_, x, y, n, n, n, c->stream);
+    if (st != ADI_OK) return fail(c, st, "network forward");
+    const int* flag = nullptr;
+    if (gate > 0.f) {
+      HIPCHK(c, nn::launch_gate(y, c->D * nn::kOutputs, partial, kClosureBlocks, gate, c->cl_flag,
+                                c->cl_flag + 1, c->stream));
+      flag = c->cl_flag;
+    }
+    HIPCHK(c, enqueue_apply(c, y, scale, flag));
+  }
+  c->cl_marked = true;
+  c->t += nsteps * c->dt;
+  return ADI_OK;
+}
+
+int adi_closure_rejected(adi_ctx* c, int* count) {
+  if (!c || !count) return ADI_EINVAL;
+  *count = 0;
+  if (!c->cl_flag) return ADI_OK;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, hipMemcpy(count, c->cl_flag + 1, sizeof(int), hipMemcpyDeviceToHost));
+  return ADI_OK;
 }
 
 }  // extern "C"

@@ -148,3 +148,35 @@ class Solver:
         a = self._arr(rhs, 3 * self.n ** 3).copy()
         self._check(self.lib.adi_solve(self.h, int(stage), int(sub), _lib.dptr(a)))
         return a.reshape(3, self.n, self.n, self.n)
+
+    # -- learned closure (solver side) ----------------------------------------
+    def copy_state_from(self, other: "Solver"):
+        """Device copy of other's state and time into this solver (same n)."""
+        self._check(self.lib.adi_copy_state(self.h, other.h))
+
+    def closure_mark(self):
+        """Remember the current state as the state before a coarse step."""
+        self._check(self.lib.adi_closure_mark(self.h))
+
+    def closure_features(self, x, scale):
+        """x: float32 device tensor [n^3, 15]; scale: float32 device tensor [1]."""
+        self._check(self.lib.adi_closure_features(self.h, ctypes.c_void_p(x.data_ptr()),
+                                                  ctypes.c_void_p(scale.data_ptr())))
+
+    def closure_target(self, fine: "Solver", scale, t):
+        """t[v][c] = (fine - self) / scale (float32 device tensors)."""
+        self._check(self.lib.adi_closure_target(fine.h, self.h, ctypes.c_void_p(scale.data_ptr()),
+                                                ctypes.c_void_p(t.data_ptr())))
+
+    def closure_apply(self, y, scale):
+        self._check(self.lib.adi_closure_apply(self.h, ctypes.c_void_p(y.data_ptr()),
+                                               ctypes.c_void_p(scale.data_ptr())))
+
+    def step_closure(self, net, nsteps: int = 1, gate: float = 0.0):
+        """nsteps coarse steps, each followed by the network's correction."""
+        self._check(self.lib.adi_step_closure(self.h, net.h, int(nsteps), float(gate)))
+
+    def closure_rejected(self) -> int:
+        c = ctypes.c_int()
+        self._check(self.lib.adi_closure_rejected(self.h, ctypes.byref(c)))
+        return c.value

@@ -97,3 +97,15 @@ def test_host_validation_errors(lib):
         assert lib.adi_factor(h, -1.0) == _lib.ADI_EINVAL
     finally:
         lib.adi_destroy(h)
+
+
+def test_network_host_validation(lib):
+    h = ctypes.c_void_p()
+    assert lib.adi_nn_create(ctypes.byref(h), 0, 32, 6, None) == _lib.ADI_EINVAL
+    assert lib.adi_nn_create(ctypes.byref(h), 17, 32, 6, None) == _lib.ADI_EINVAL
+    assert lib.adi_nn_create(ctypes.byref(h), 16, 16, 6, None) == _lib.ADI_EINVAL
+    assert lib.adi_nn_create(ctypes.byref(h), 16, 32, 0, None) == _lib.ADI_EINVAL
+    assert lib.adi_nn_create(None, 16, 32, 6, None) == _lib.ADI_EINVAL
+    assert lib.adi_nn_param_count(None) == _lib.ADI_EINVAL
+    assert lib.adi_copy_state(None, None) == _lib.ADI_EINVAL
+    assert lib.adi_step_closure(None, None, 1, ctypes.c_float(0.0)) == _lib.ADI_EINVAL
