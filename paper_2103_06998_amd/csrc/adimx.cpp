@@ -70,6 +70,8 @@ struct adi_ctx {
   double* zw64 = nullptr;   // same in float64
   double* fb64 = nullptr;   // factor bands: Mdir, Sdir (n (2p+1) each)
   void* shL[2] = {}, *shU[2] = {}, *shD[2] = {};  // shared factors: [0] free, [1] Dirichlet
+  void* spk[2] = {};        // partitioned-solve data of the shared factors (same variants)
+  bool spike_ok = false;    // spk holds valid data for the current factorisation
   void* mL[6] = {}, *mU[6] = {}, *mD[6] = {};     // per-line factors, system (s-1)*3 + c
   double* minratio = nullptr;
   double* d_t = nullptr;
@@ -139,6 +141,10 @@ size_t layout(adi_ctx* c, unsigned char* base) {
     c->shL[v] = take(size_t(n) * P * es);
     c->shU[v] = take(size_t(n) * P * es);
     c->shD[v] = take(size_t(n) * es);
+  }
+  {
+    const int q = 2 * P * (kSpikeS - 1);
+    for (int v = 0; v < 2; ++v) c->spk[v] = take((size_t(n) * (4 * P + 1) + size_t(q) * q) * es);
   }
   for (int s = 0; s < 6; ++s) {
     c->mL[s] = take(size_t(P) * D * es);
@@ -263,6 +269,7 @@ SweepDesc desc_for(adi_ctx* c, int kindH, int sub, int comp_i, int axis, void* i
     d.L = c->shL[v];
     d.U = c->shU[v];
     d.D = c->shD[v];
+    d.spk = c->spike_ok ? c->spk[v] : nullptr;
     d.modified = 0;
   }
   return d;
@@ -312,6 +319,7 @@ hipError_t enqueue_solves(adi_ctx* c, int kindH, int sub, void* buf, void* final
       a.tick_t = nullptr;
       int nmod = 0;
       for (int q = 0; q < nd; ++q) nmod += a.d[q].modified;
+      a.spike = (c->spike_ok && nmod == 0) ? 1 : 0;
       hipError_t e = timed(c, s, xgroup ? kKindSweepX : kKindSweepYZ, nd, nmod,
                            [&] { return launch_sweep<T>(c->p, nd, a, s); });
       if (e != hipSuccess) return e;
@@ -387,6 +395,7 @@ hipError_t enqueue_step_t(adi_ctx* c, hipStream_t s) {
         w.n = c->n;
         w.nlines = c->n * c->n;
         w.xaxis = ax == 0;
+        w.spike = c->spike_ok ? 1 : 0;
         if (sub == 2 && ax == 2) {
           w.tick_t = c->d_t;
           w.tick_dt = c->dt;
@@ -637,6 +646,27 @@ int adi_factor(adi_ctx* c, double dt) {
     if ((st = upload(c, c->shL[v], L)) != ADI_OK) return st;
     if ((st = upload(c, c->shU[v], U)) != ADI_OK) return st;
     if ((st = upload(c, c->shD[v], Dinv)) != ADI_OK) return st;
+  }
+  // partitioned-solve data of the same matrices (long lines only); any
+  // failed self-check keeps the one-lane-per-line solve
+  c->spike_ok = false;
+  if (n >= kSpikeMinN && n <= kSpikeMaxN) {
+    bool ok = true;
+    std::vector<double> pack[2];
+    for (int v = 0; v < 2 && ok; ++v) {
+      std::vector<double> band = g.M;
+      if (v) apply_dirichlet(band, n, p);
+      SpikeData sd;
+      ok = spike_prepare(band, n, p, kSpikeS, sd);
+      if (!ok) break;
+      for (const std::vector<double>* part : {&sd.L, &sd.DU, &sd.D, &sd.V, &sd.W, &sd.R})
+        pack[v].insert(pack[v].end(), part->begin(), part->end());
+    }
+    if (ok) {
+      for (int v = 0; v < 2; ++v)
+        if ((st = upload(c, c->spk[v], pack[v])) != ADI_OK) return st;
+      c->spike_ok = true;
+    }
   }
 
   // per-row coefficients (material attached to test functions), with the

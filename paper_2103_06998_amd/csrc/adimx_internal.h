@@ -10,7 +10,10 @@
 
 namespace adimx {
 
-constexpr int kMaxP = 4;  // largest supported B-spline degree
+constexpr int kMaxP = 4;    // largest supported B-spline degree
+constexpr int kSpikeS = 4;  // segments per line of the partitioned line solve
+// Lines of n rows use the partitioned solve when kSpikeMinN <= n <= kSpikeMaxN.
+constexpr int kSpikeMinN = 48, kSpikeMaxN = 288;
 
 // ---------------------------------------------------------------- host (FP64)
 struct Gram1D {
@@ -28,6 +31,21 @@ void apply_dirichlet(std::vector<double>& band, int n, int p);
 double band_lu(const std::vector<double>& band, int n, int p, std::vector<double>& L,
                std::vector<double>& Uoff, std::vector<double>& Uinv);
 std::vector<double> greville(int N, int p);
+
+// Partitioned (SPIKE) solve data of one shared banded matrix split into S
+// row segments [spike_boundary(n,S,i), spike_boundary(n,S,i+1)):
+// block-diagonal LU (L, DU = D*U, D as band_lu, couplings across segment
+// boundaries removed), spikes V, W ([r*p + k]) and the inverse R (q x q,
+// q = 2p(S-1), row-major) of the reduced system on the unknowns
+// z = [U_0, T_1, U_1, T_2, ..., U_{S-2}, T_{S-1}] (U_i: bottom p rows of
+// segment i, T_i: top p rows).  Returns false if a segment is shorter than
+// 2p, a pivot is tiny, or a self-check against the direct solve fails.
+struct SpikeData {
+  int S = 0, q = 0;
+  std::vector<double> L, DU, D, V, W, R;
+};
+int spike_boundary(int n, int S, int i);
+bool spike_prepare(const std::vector<double>& band, int n, int p, int S, SpikeData& out);
 void basis_at(int N, int p, double x, int* first, double* vals);
 
 // ---------------------------------------------------------------- kernels
@@ -72,6 +90,8 @@ struct SweepDesc {
   const void* L;          // factors; shared: [r*P + k-1], modified: [((k-1)*n + r)*nlines + l]
   const void* U;          // D * U (pre-scaled upper factor), same layout as L
   const void* D;          // inverse diagonal; shared: [r], modified: [r*nlines + l]
+  const void* spk;        // shared factors only: partitioned-solve data (L, DU, D, V, W
+                          // as [r*P + k] / [r], then R, q x q), or null
   int modified;           // 0 = shared factors, 1 = per-line factors
 };
 
@@ -80,6 +100,7 @@ struct SweepArgs {
   int n;
   int nlines;
   int xaxis;              // 1: all descriptors are x lines (transposing kernel)
+  int spike;              // 1: shared-factor lines solved in kSpikeS segments each
   double* tick_t;         // if non-null, block (0,0) thread 0 does *tick_t += tick_dt
   double tick_dt;
 };

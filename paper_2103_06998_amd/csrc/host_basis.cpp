@@ -15,6 +15,7 @@
 // Band storage: band[r * (2p+1) + d] = X[r][r + d - p].
 #include "adimx_internal.h"
 
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -195,6 +196,172 @@ double band_lu(const std::vector<double>& band, int n, int p, std::vector<double
     Uinv[i] = 1.0 / Ud[i];
   }
   return minratio;
+}
+
+// ------------------------------------------------------------ partitioned solve
+// A banded matrix (bandwidth p each side) split into S row segments
+// [b_i, b_{i+1}) is solved as: local solves with the block diagonal, then a
+// small reduced system for the p unknowns on either side of every segment
+// boundary, then a correction with the spikes (the block diagonal's inverse
+// applied to the couplings across the boundaries).
+namespace {
+
+// Forward / backward substitution with the factors of band_lu (DU = D * U).
+void lu_solve(const std::vector<double>& L, const std::vector<double>& DU,
+              const std::vector<double>& D, int n, int p, std::vector<double>& x) {
+  for (int r = 0; r < n; ++r)
+    for (int k = 1; k <= p && r - k >= 0; ++k) x[r] -= L[size_t(r) * p + k - 1] * x[r - k];
+  for (int r = n - 1; r >= 0; --r) {
+    double s = D[r] * x[r];
+    for (int k = 1; k <= p && r + k < n; ++k) s -= DU[size_t(r) * p + k - 1] * x[r + k];
+    x[r] = s;
+  }
+}
+
+// Gauss-Jordan inverse with partial pivoting (q x q, row-major); false if singular.
+bool dense_inverse(std::vector<double> a, int q, std::vector<double>& inv) {
+  inv.assign(size_t(q) * q, 0.0);
+  for (int i = 0; i < q; ++i) inv[size_t(i) * q + i] = 1.0;
+  for (int c = 0; c < q; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < q; ++r)
+      if (std::fabs(a[size_t(r) * q + c]) > std::fabs(a[size_t(piv) * q + c])) piv = r;
+    if (!(std::fabs(a[size_t(piv) * q + c]) > 1e-300)) return false;
+    if (piv != c)
+      for (int j = 0; j < q; ++j) {
+        std::swap(a[size_t(c) * q + j], a[size_t(piv) * q + j]);
+        std::swap(inv[size_t(c) * q + j], inv[size_t(piv) * q + j]);
+      }
+    const double d = 1.0 / a[size_t(c) * q + c];
+    for (int j = 0; j < q; ++j) {
+      a[size_t(c) * q + j] *= d;
+      inv[size_t(c) * q + j] *= d;
+    }
+    for (int r = 0; r < q; ++r) {
+      if (r == c) continue;
+      const double f = a[size_t(r) * q + c];
+      if (f == 0.0) continue;
+      for (int j = 0; j < q; ++j) {
+        a[size_t(r) * q + j] -= f * a[size_t(c) * q + j];
+        inv[size_t(r) * q + j] -= f * inv[size_t(c) * q + j];
+      }
+    }
+  }
+  return true;
+}
+
+}  // namespace
+
+int spike_boundary(int n, int S, int i) { return int((long(i) * n) / S); }
+
+bool spike_prepare(const std::vector<double>& band, int n, int p, int S, SpikeData& out) {
+  const int w = 2 * p + 1, q = 2 * p * (S - 1);
+  for (int i = 0; i < S; ++i)
+    if (spike_boundary(n, S, i + 1) - spike_boundary(n, S, i) < 2 * p) return false;
+  std::vector<int> seg(n);
+  for (int i = 0; i < S; ++i)
+    for (int r = spike_boundary(n, S, i); r < spike_boundary(n, S, i + 1); ++r) seg[r] = i;
+  auto A = [&](int r, int c) -> double {
+    if (c < 0 || c >= n || c - r > p || r - c > p) return 0.0;
+    return band[size_t(r) * w + (c - r + p)];
+  };
+  // block diagonal (couplings across segment boundaries removed) and its LU
+  std::vector<double> blk(band);
+  for (int r = 0; r < n; ++r)
+    for (int d = 0; d < w; ++d) {
+      const int c = r + d - p;
+      if (c >= 0 && c < n && seg[c] != seg[r]) blk[size_t(r) * w + d] = 0.0;
+    }
+  std::vector<double> L, U, Dinv;
+  const double ratio = band_lu(blk, n, p, L, U, Dinv);
+  if (!(ratio > 1e-14)) return false;
+  for (int r = 0; r < n; ++r)
+    for (int k = 0; k < p; ++k) U[size_t(r) * p + k] *= Dinv[r];
+  // spikes: V[:, k] = blockdiag^-1 (coupling to x[b_{i+1} + k]) for rows of
+  // segment i < S-1; W[:, k] = blockdiag^-1 (coupling to x[b_i - p + k]) for i > 0
+  std::vector<double> V(size_t(n) * p, 0.0), Wv(size_t(n) * p, 0.0), col(n);
+  for (int k = 0; k < p; ++k) {
+    for (int r = 0; r < n; ++r) {
+      const int i = seg[r];
+      col[r] = (i < S - 1) ? A(r, spike_boundary(n, S, i + 1) + k) : 0.0;
+    }
+    lu_solve(L, U, Dinv, n, p, col);
+    for (int r = 0; r < n; ++r) V[size_t(r) * p + k] = col[r];
+    for (int r = 0; r < n; ++r) {
+      const int i = seg[r];
+      col[r] = (i > 0) ? A(r, spike_boundary(n, S, i) - p + k) : 0.0;
+    }
+    lu_solve(L, U, Dinv, n, p, col);
+    for (int r = 0; r < n; ++r) Wv[size_t(r) * p + k] = col[r];
+  }
+  // reduced system on z = [U_0, T_1, U_1, T_2, ..., U_{S-2}, T_{S-1}] (p each):
+  // U_i = bottom p rows of segment i, T_i = top p rows of segment i;
+  // x_i = g_i - V_i T_{i+1} - W_i U_{i-1} restricted to those rows.
+  auto zU = [&](int i, int j) { return 2 * p * i + j; };
+  auto zT = [&](int i, int j) { return 2 * p * (i - 1) + p + j; };
+  std::vector<double> K(size_t(q) * q, 0.0);
+  for (int i = 0; i < S; ++i) {
+    const int b0 = spike_boundary(n, S, i), b1 = spike_boundary(n, S, i + 1);
+    for (int side = 0; side < 2; ++side) {  // 0: U_i (bottom rows), 1: T_i (top rows)
+      if (side == 0 && i == S - 1) continue;
+      if (side == 1 && i == 0) continue;
+      for (int j = 0; j < p; ++j) {
+        const int r = side == 0 ? b1 - p + j : b0 + j;
+        const int row = side == 0 ? zU(i, j) : zT(i, j);
+        K[size_t(row) * q + row] += 1.0;
+        for (int k = 0; k < p; ++k) {
+          if (i < S - 1) K[size_t(row) * q + zT(i + 1, k)] += V[size_t(r) * p + k];
+          if (i > 0) K[size_t(row) * q + zU(i - 1, k)] += Wv[size_t(r) * p + k];
+        }
+      }
+    }
+  }
+  std::vector<double> R;
+  if (!dense_inverse(K, q, R)) return false;
+
+  // self-check against the direct banded solve on a fixed right-hand side
+  std::vector<double> La, Ua, Da;
+  band_lu(band, n, p, La, Ua, Da);
+  for (int r = 0; r < n; ++r)
+    for (int k = 0; k < p; ++k) Ua[size_t(r) * p + k] *= Da[r];
+  std::vector<double> b(n), ref(n), g(n);
+  for (int r = 0; r < n; ++r) b[r] = std::sin(0.7 * r + 0.3) + 0.25 * std::cos(2.1 * r);
+  ref = b;
+  lu_solve(La, Ua, Da, n, p, ref);
+  g = b;
+  lu_solve(L, U, Dinv, n, p, g);
+  std::vector<double> gz(q), z(q, 0.0);
+  for (int i = 0; i + 1 < S; ++i) {
+    const int b1 = spike_boundary(n, S, i + 1);
+    for (int j = 0; j < p; ++j) {
+      gz[zU(i, j)] = g[b1 - p + j];
+      gz[zT(i + 1, j)] = g[b1 + j];
+    }
+  }
+  for (int r = 0; r < q; ++r)
+    for (int c = 0; c < q; ++c) z[r] += R[size_t(r) * q + c] * gz[c];
+  double err = 0.0, nrm = 0.0;
+  for (int r = 0; r < n; ++r) {
+    const int i = seg[r];
+    double x = g[r];
+    for (int k = 0; k < p; ++k) {
+      if (i < S - 1) x -= V[size_t(r) * p + k] * z[zT(i + 1, k)];
+      if (i > 0) x -= Wv[size_t(r) * p + k] * z[zU(i - 1, k)];
+    }
+    err = std::max(err, std::fabs(x - ref[r]));
+    nrm = std::max(nrm, std::fabs(ref[r]));
+  }
+  if (!(err <= 1e-12 * nrm)) return false;
+
+  out.S = S;
+  out.q = q;
+  out.L = std::move(L);
+  out.DU = std::move(U);
+  out.D = std::move(Dinv);
+  out.V = std::move(V);
+  out.W = std::move(Wv);
+  out.R = std::move(R);
+  return true;
 }
 
 std::vector<double> greville(int N, int p) {

@@ -320,6 +320,22 @@ __global__ __launch_bounds__(kRhsThreads) void rhs_kernel(RhsArgs<TC> a,
   }
 }
 
+// Copy count values from global memory to LDS with NTH threads, eight loads
+// in flight per thread.
+template <typename T, int NTH>
+__device__ __forceinline__ void stage_batched(T* dst, const T* __restrict__ src, int count,
+                                              int tid) {
+  constexpr int B = 8;
+  for (int base = tid; base < count; base += NTH * B) {
+    T v[B];
+#pragma unroll
+    for (int j = 0; j < B; ++j) v[j] = src[min(base + j * NTH, count - 1)];
+#pragma unroll
+    for (int j = 0; j < B; ++j)
+      if (base + j * NTH < count) dst[base + j * NTH] = v[j];
+  }
+}
+
 // ------------------------------------------------------------ sweeps
 // One wave (64 lanes) solves 64 lines: lane = line.  The 64 x n tile is
 // staged through LDS (row pitch 65 elements: conflict-free column access and
@@ -378,14 +394,9 @@ __global__ __launch_bounds__(64) void sweep_kernel(SweepArgs a) {
   const int nreg = min(n, kRR);
 
   if (!MOD) {
-    const T* Lf = static_cast<const T*>(ds.L);
-    const T* Uf = static_cast<const T*>(ds.U);
-    const T* Df = static_cast<const T*>(ds.D);
-    for (int i = lane; i < n * P; i += 64) {
-      sfac[i] = Lf[i];
-      sfac[n * P + i] = Uf[i];
-    }
-    for (int i = lane; i < n; i += 64) sfac[2 * n * P + i] = Df[i];
+    stage_batched<T, 64>(sfac, static_cast<const T*>(ds.L), n * P, lane);
+    stage_batched<T, 64>(sfac + n * P, static_cast<const T*>(ds.U), n * P, lane);
+    stage_batched<T, 64>(sfac + 2 * n * P, static_cast<const T*>(ds.D), n, lane);
   }
 
   // x lines: copy columns [c0, c1) of the nll contiguous lines into
@@ -598,6 +609,144 @@ __global__ __launch_bounds__(64) void sweep_kernel(SweepArgs a) {
   if (a.tick_t && blockIdx.x == 0 && blockIdx.y == 0 && lane == 0) *a.tick_t += a.tick_dt;
 }
 
+// ------------------------------------------------------------ partitioned sweep
+// Shared-factor lines, each split into kSpikeS row segments solved by the
+// kSpikeS waves of a block (wave = segment, lane = line, 64 lines per
+// block); a segment's rows stay in registers.  Per line:
+//   1. g = A_s^{-1} b on every segment (block-diagonal LU, forward and
+//      backward recurrences of m = n / kSpikeS rows instead of n);
+//   2. the p values at both ends of every segment go through LDS, and each
+//      segment forms the 2p interface unknowns it needs from the
+//      precomputed inverse R of the reduced system: T (top p rows of the
+//      next segment) and U (bottom p rows of the previous one);
+//   3. x = g - V T - W U with the precomputed spikes V, W.
+// The factors, spikes and R of the descriptor are staged in LDS (broadcast
+// reads: every lane of a wave reads the same row).
+template <typename T, int P, bool XAX, int MR>
+__global__ __launch_bounds__(64 * kSpikeS) void spike_kernel(SweepArgs a) {
+  constexpr int S = kSpikeS, Q = 2 * P * (S - 1);
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* sf = reinterpret_cast<T*>(smem);
+  const int n = a.n, nl = a.nlines;
+  const int nf = n * (4 * P + 1) + Q * Q;
+  T* gex = sf + nf;  // [Q][64] boundary values of g
+  const SweepDesc& ds = a.d[blockIdx.y];
+  const int tid = threadIdx.x, seg = tid >> 6, lane = tid & 63;
+  const T* sL = sf;
+  const T* sDU = sf + n * P;
+  const T* sD = sf + 2 * n * P;
+  const T* sV = sD + n;
+  const T* sW = sV + n * P;
+  const T* sR = sW + n * P;
+
+  const T* __restrict__ in = static_cast<const T*>(ds.in);
+  T* __restrict__ out = static_cast<T*>(ds.out);
+  const T* __restrict__ accp = static_cast<const T*>(ds.acc);
+  const int l = blockIdx.x * 64 + lane;
+  const bool act = l < nl;
+  const int lc = act ? l : 0;
+  const size_t n2 = size_t(n) * n;
+  size_t lbase, rstride;
+  if (XAX) {
+    lbase = size_t(lc) * n;
+    rstride = 1;
+  } else if (ds.axis == 1) {
+    lbase = size_t(lc % n) + size_t(lc / n) * n2;
+    rstride = n;
+  } else {
+    lbase = size_t(lc);
+    rstride = n2;
+  }
+  const int b0 = (seg * n) / S, b1 = ((seg + 1) * n) / S, m = b1 - b0;  // m <= MR
+
+  // unconditional loads (rows past the segment repeat its last row) keep
+  // every load of the segment in flight at once
+  T y[MR];
+#pragma unroll
+  for (int r = 0; r < MR; ++r) y[r] = in[lbase + size_t(b0 + min(r, m - 1)) * rstride];
+  stage_batched<T, 64 * S>(sf, static_cast<const T*>(ds.spk), nf, tid);
+  __syncthreads();  // factors staged
+
+  T h[P];
+#pragma unroll
+  for (int k = 0; k < P; ++k) h[k] = T(0);
+#pragma unroll
+  for (int r = 0; r < MR; ++r) {
+    if (r < m) {  // uniform
+      const T* Lr = sL + (b0 + r) * P;
+      T s = y[r];
+#pragma unroll
+      for (int k = P - 1; k >= 0; --k) s -= Lr[k] * h[k];
+#pragma unroll
+      for (int k = P - 1; k > 0; --k) h[k] = h[k - 1];
+      h[0] = s;
+      y[r] = s;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < P; ++k) h[k] = T(0);
+#pragma unroll
+  for (int r = MR - 1; r >= 0; --r) {
+    if (r < m) {
+      const int g = b0 + r;
+      T s = sD[g] * y[r];
+#pragma unroll
+      for (int k = P - 1; k >= 0; --k) s -= sDU[g * P + k] * h[k];
+#pragma unroll
+      for (int k = P - 1; k > 0; --k) h[k] = h[k - 1];
+      h[0] = s;
+      y[r] = s;
+    }
+  }
+
+  // boundary values: z layout [U_0, T_1, U_1, T_2, ...], p each
+#pragma unroll
+  for (int r = 0; r < MR; ++r) {
+    if (seg > 0 && r < P) gex[(2 * P * (seg - 1) + P + r) * 64 + lane] = y[r];
+    if (seg < S - 1 && r >= m - P && r < m) gex[(2 * P * seg + r - (m - P)) * 64 + lane] = y[r];
+  }
+  __syncthreads();
+  T tn[P], up[P];
+#pragma unroll
+  for (int k = 0; k < P; ++k) {
+    tn[k] = T(0);
+    up[k] = T(0);
+  }
+  if (seg < S - 1) {
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+      const T* Rr = sR + (2 * P * seg + P + k) * Q;
+      T s = T(0);
+#pragma unroll
+      for (int c = 0; c < Q; ++c) s += Rr[c] * gex[c * 64 + lane];
+      tn[k] = s;
+    }
+  }
+  if (seg > 0) {
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+      const T* Rr = sR + (2 * P * (seg - 1) + k) * Q;
+      T s = T(0);
+#pragma unroll
+      for (int c = 0; c < Q; ++c) s += Rr[c] * gex[c * 64 + lane];
+      up[k] = s;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < MR; ++r) {
+    if (r < m) {
+      const int g = b0 + r;
+      T x = y[r];
+#pragma unroll
+      for (int k = 0; k < P; ++k) x -= sV[g * P + k] * tn[k] + sW[g * P + k] * up[k];
+      const size_t o = lbase + size_t(g) * rstride;
+      if (accp) x += accp[o];
+      if (act) out[o] = x;
+    }
+  }
+  if (a.tick_t && blockIdx.x == 0 && blockIdx.y == 0 && tid == 0) *a.tick_t += a.tick_dt;
+}
+
 // ------------------------------------------------------------ factorisation
 // Pivot-free banded Doolittle LU of the material-modified 1D matrices, one
 // line per thread, in float64.  Row r of line l is Mb[r,:] + alpha[pos] Sb[r,:]
@@ -745,12 +894,40 @@ hipError_t launch_sweep_k(int ndesc, const SweepArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <typename T, int P, bool XAX, int MR>
+hipError_t launch_spike_k(int ndesc, const SweepArgs& a, hipStream_t s) {
+  constexpr int Q = 2 * P * (kSpikeS - 1);
+  const size_t lds = (size_t(a.n) * (4 * P + 1) + Q * Q + size_t(Q) * 64) * sizeof(T);
+  dim3 grid((a.nlines + 63) / 64, ndesc);
+  auto k = spike_kernel<T, P, XAX, MR>;
+  hipError_t e = set_lds(k, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k, grid, dim3(64 * kSpikeS), lds, s, a);
+  return hipGetLastError();
+}
+
+template <typename T, int P, bool XAX>
+hipError_t launch_spike_x(int ndesc, const SweepArgs& a, hipStream_t s) {
+  // register rows per segment: ceil(n / kSpikeS)
+  const int m = (a.n + kSpikeS - 1) / kSpikeS;
+  if (m <= 40) return launch_spike_k<T, P, XAX, 40>(ndesc, a, s);
+  if (m <= 72) return launch_spike_k<T, P, XAX, 72>(ndesc, a, s);
+  return hipErrorInvalidValue;
+}
+
 template <typename T, int P>
 hipError_t launch_sweep_p(int ndesc, const SweepArgs& a, hipStream_t s) {
   // every descriptor of one launch is either modified or shared
   const bool mod = a.d[0].modified != 0;
   for (int i = 1; i < ndesc; ++i)
     if ((a.d[i].modified != 0) != mod) return hipErrorInvalidValue;
+  if (a.spike && !mod) {
+    if (a.n < kSpikeMinN || a.n > kSpikeMaxN) return hipErrorInvalidValue;
+    for (int i = 0; i < ndesc; ++i)
+      if (!a.d[i].spk) return hipErrorInvalidValue;
+    return a.xaxis ? launch_spike_x<T, P, true>(ndesc, a, s)
+                   : launch_spike_x<T, P, false>(ndesc, a, s);
+  }
   if (a.xaxis)
     return mod ? launch_sweep_k<T, P, true, true>(ndesc, a, s)
                : launch_sweep_k<T, P, true, false>(ndesc, a, s);

@@ -89,9 +89,22 @@ def test_rhs_stage(Solver, N, p, stage, sub):
         assert rel_l2(got[c], ref[c]) <= TOL64, (c, rel_l2(got[c], ref[c]))
 
 
-@pytest.mark.parametrize("N,p", [(1, 2), (3, 1), (5, 2), (4, 3), (9, 3), (33, 2)])
+# n = N + p >= 48 takes the partitioned (4 segments per line) solve for the
+# shared-factor axes: n = 48, 54, 59 and 72 cover even and ragged segments
+# and every degree; (160, 2) takes the longer register segments (n = 162).
+@pytest.mark.parametrize("N,p", [(1, 2), (3, 1), (5, 2), (4, 3), (9, 3), (33, 2), (45, 3),
+                                 (50, 4), (58, 1), (70, 2)])
 @pytest.mark.parametrize("stage,sub", [(0, 1), (0, 2), (1, 1), (1, 2)])
 def test_solve_stage(Solver, N, p, stage, sub):
+    _solve_stage(Solver, N, p, stage, sub)
+
+
+@pytest.mark.parametrize("stage,sub", [(0, 2), (1, 1)])
+def test_solve_stage_long_lines(Solver, stage, sub):
+    _solve_stage(Solver, 160, 2, stage, sub)
+
+
+def _solve_stage(Solver, N, p, stage, sub):
     eps, mu, sig, _ = random_setup(N, p, seed=7 + N + p, with_src=False)
     dt = 0.11
     prob = maxwell.Problem(N, p, eps, mu, sig, dt)
@@ -108,7 +121,7 @@ def test_solve_stage(Solver, N, p, stage, sub):
 
 
 @pytest.mark.parametrize("N,p,steps", [(1, 1, 3), (2, 3, 3), (3, 2, 4), (6, 2, 3), (5, 3, 3),
-                                       (37, 3, 2)])
+                                       (37, 3, 2), (47, 2, 2)])
 def test_full_steps_random_material(Solver, N, p, steps):
     eps, mu, sig, src = random_setup(N, p, seed=100 + N)
     dt = 0.5 / N
