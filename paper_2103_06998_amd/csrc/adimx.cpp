@@ -176,20 +176,21 @@ int upload(adi_ctx* c, void* dst, const std::vector<double>& src) {
   return ADI_OK;
 }
 
-// Output planes per RHS block: the tile grid is ceil(n/32) x ceil(n/8) x
-// ceil(n/zchunk) blocks of 768 threads (one resident per CU); pick the chunk
-// (>= 8 planes, to bound the 2p-plane halo) whose block count best fills
-// whole rounds of 256 CUs.
+// Output planes per RHS block: the grid is 3 ceil(n/32) ceil(n/8)
+// ceil(n/zchunk) blocks of 256 threads (one per tile and output component),
+// about two resident per CU; pick the chunk (>= 8 planes, to bound the
+// 2p-plane halo) whose block count best fills whole rounds of 512 slots.
 int pick_zchunk(int n) {
-  const long xy = long((n + 31) / 32) * ((n + 7) / 8);
+  const long xy = 3L * ((n + 31) / 32) * ((n + 7) / 8);
+  const long slots = 512;
   int best = n;
   double best_eff = -1.0;
-  for (int z = 8; z <= std::max(8, n); ++z) {
-    const long nz = (n + z - 1) / z;
-    const long blocks = xy * nz;
-    const long rounds = (blocks + 255) / 256;
-    // efficiency of the CU rounds, slightly favouring fewer halo planes
-    const double eff = double(blocks) / double(rounds * 256) * (double(z) / (z + 6.0));
+  for (int nz = 1; nz <= std::max(1, n / 8); ++nz) {
+    const int z = (n + nz - 1) / nz;  // balanced chunks
+    const long blocks = xy * ((n + z - 1) / z);
+    const long rounds = (blocks + slots - 1) / slots;
+    // efficiency of the rounds, slightly favouring fewer halo planes
+    const double eff = double(blocks) / double(rounds * slots) * (double(z) / (z + 6.0));
     if (eff > best_eff + 1e-9) {
       best_eff = eff;
       best = z;

@@ -76,28 +76,44 @@ __host__ __device__ constexpr Term get_term(int i) {
   return sub2 ? px_sub2[i - 12] : px_sub1[i - 12];
 }
 
-// Distinct (field, y-operator) pairs: each is applied once per plane.
-struct PairTab {
-  int np = 0;
-  int field[24] = {};
-  int yop[24] = {};
-  int of_term[24] = {};
+// Per output component: the input fields it reads (local slots) and its
+// distinct (field, y-operator) pairs, each applied once per plane.
+struct CompTab {
+  int nf[3] = {};           // fields read by component c
+  int field[3][8] = {};     // slot -> field index
+  int np[3] = {};           // pairs of component c
+  int pslot[3][12] = {};    // pair -> field slot
+  int pyop[3][12] = {};     // pair -> y operator
+  int term_pair[24] = {};   // term -> pair index within its component
+  int maxnf = 0, maxnp = 0;
 };
 
 template <int STAGE>
-constexpr PairTab make_pairs() {
-  PairTab t{};
+constexpr CompTab make_comp_tab() {
+  CompTab t{};
   for (int i = 0; i < StageInfo<STAGE>::NT; ++i) {
     const Term tm = get_term<STAGE>(i);
-    int found = -1;
-    for (int k = 0; k < t.np; ++k)
-      if (t.field[k] == tm.field && t.yop[k] == tm.y) found = k;
-    if (found < 0) {
-      found = t.np++;
-      t.field[found] = tm.field;
-      t.yop[found] = tm.y;
+    const int c = tm.out;
+    int slot = -1;
+    for (int k = 0; k < t.nf[c]; ++k)
+      if (t.field[c][k] == tm.field) slot = k;
+    if (slot < 0) {
+      slot = t.nf[c]++;
+      t.field[c][slot] = tm.field;
     }
-    t.of_term[i] = found;
+    int pr = -1;
+    for (int k = 0; k < t.np[c]; ++k)
+      if (t.pslot[c][k] == slot && t.pyop[c][k] == tm.y) pr = k;
+    if (pr < 0) {
+      pr = t.np[c]++;
+      t.pslot[c][pr] = slot;
+      t.pyop[c][pr] = tm.y;
+    }
+    t.term_pair[i] = pr;
+  }
+  for (int c = 0; c < 3; ++c) {
+    t.maxnf = t.nf[c] > t.maxnf ? t.nf[c] : t.maxnf;
+    t.maxnp = t.np[c] > t.maxnp ? t.np[c] : t.maxnp;
   }
   return t;
 }
@@ -112,45 +128,50 @@ __device__ __forceinline__ void static_for(F&& f) {
 }
 
 constexpr int kTX = 32, kTY = 8, kCols = kTX * kTY;
-constexpr int kRhsThreads = 3 * kCols;  // one group of 4 waves per output component
-constexpr int kPrefetch = 2;            // input planes loaded ahead of use
+constexpr int kRhsThreads = kCols;  // one block per (tile, output component)
+constexpr int kPrefetch = 2;        // input planes loaded ahead of use
 
 // The residual stages keep four accumulator groups per thread; their x band
 // rows are read from LDS instead of registers to stay clear of spills.
 template <int STAGE>
 constexpr bool xband_in_lds() { return StageInfo<STAGE>::NG == 4; }
 
+// LDS of one RHS block: staged plane, y-pass results, x band rows (residual
+// stages), the y band rows of the tile and the z weights of the chunk's
+// input planes.
 template <typename TC, int P, int STAGE>
-constexpr size_t rhs_lds_bytes() {
+size_t rhs_lds_bytes(int zchunk) {
   constexpr int HX = kTX + 2 * P, HY = kTY + 2 * P, W = 2 * P + 1;
-  constexpr PairTab PT = make_pairs<STAGE>();
-  return sizeof(TC) * (size_t(StageInfo<STAGE>::NF) * HY * HX + size_t(PT.np) * kTY * HX +
-                       (xband_in_lds<STAGE>() ? 4 * kTX * W : 0));
+  constexpr CompTab CT = make_comp_tab<STAGE>();
+  return sizeof(TC) * (size_t(CT.maxnf) * HY * HX + size_t(CT.maxnp) * kTY * HX +
+                       (xband_in_lds<STAGE>() ? 4 * kTX * W : 0) + size_t(4) * kTY * W +
+                       size_t(zchunk + 2 * P) * 4 * W);
 }
 
 // ------------------------------------------------------------ RHS kernel
-// Block = a kTX x kTY tile of (x, y) output columns and a chunk of kZChunk z
-// planes; its three groups of 256 threads compute the three output
-// components.  Input planes are marched along z: each plane of every input
-// field is staged (with a p-halo in x and y) in LDS (the next plane is
-// loaded into registers while the current one is processed).  The y
-// operators are applied by one wave per (field, operator) pair, each lane
-// producing a column of kTY values from 2p + kTY staged values; the x
-// operators are applied per output column with the thread's band rows in
-// registers, and each result is scattered into a register queue of 2p+1
-// pending output planes with the z operator's weights.  When the oldest
-// pending plane is complete it is scaled by the per-row coefficients and
-// written.  TI: input type, TC: arithmetic type, TO: output type.
+// Block = one output component of a kTX x kTY tile of (x, y) output columns
+// and a chunk of z planes (blockIdx.x = 3 * tile + component, so the three
+// components of a tile run side by side and share its inputs in L2).  Input
+// planes are marched along z: each plane of every field the component reads
+// is staged (with a p-halo in x and y) in LDS, the next planes are loaded
+// into registers meanwhile.  The y operators are applied by one wave per
+// (field, operator) pair, each lane producing a column of kTY values from
+// 2p + kTY staged values; the x operators are applied per output column with
+// the thread's band rows in registers, and each result is scattered into a
+// register queue of 2p+1 pending output planes with the z operator's
+// weights.  When the oldest pending plane is complete it is scaled by the
+// per-row coefficients and written.  TI: input type, TC: arithmetic type,
+// TO: output type.
 template <typename TI, typename TC, typename TO, int P, int STAGE>
 __global__ __launch_bounds__(kRhsThreads) void rhs_kernel(RhsArgs<TC> a,
                                                           const TC* __restrict__ band,
                                                           const TC* __restrict__ zw) {
   constexpr int W = 2 * P + 1, HX = kTX + 2 * P, HY = kTY + 2 * P;
-  constexpr int NT = StageInfo<STAGE>::NT, NF = StageInfo<STAGE>::NF, NG = StageInfo<STAGE>::NG;
-  constexpr PairTab PT = make_pairs<STAGE>();
-  constexpr int NP = PT.np;
+  constexpr int NT = StageInfo<STAGE>::NT, NG = StageInfo<STAGE>::NG;
+  constexpr CompTab CT = make_comp_tab<STAGE>();
   constexpr bool kE = !(STAGE == kStageH1 || STAGE == kStageH2);
-  constexpr int PLANE = NF * HY * HX;                          // staged values per plane
+  constexpr int FPL = HY * HX;                                  // staged values per field
+  constexpr int PLANE = CT.maxnf * FPL;                         // staged values per plane
   constexpr int NLD = (PLANE + kRhsThreads - 1) / kRhsThreads;  // per thread
   constexpr int NWAVES = kRhsThreads / 64;
   static_assert(HX <= 64, "one lane per staged x column in the y pass");
@@ -158,19 +179,23 @@ __global__ __launch_bounds__(kRhsThreads) void rhs_kernel(RhsArgs<TC> a,
   extern __shared__ __align__(16) unsigned char smem[];
   TC* sF = reinterpret_cast<TC*>(smem);
   TC* sG = sF + PLANE;
-  TC* sBX = sG + NP * kTY * HX;  // x band rows (residual stages only)
   constexpr bool kXL = xband_in_lds<STAGE>();
+  TC* sBX = sG + CT.maxnp * kTY * HX;       // x band rows (residual stages only)
+  TC* sYB = sBX + (kXL ? 4 * kTX * W : 0);  // y band rows [op][yy][d] of the tile
+  TC* sZW = sYB + 4 * kTY * W;              // z weights [plane - kbeg][op][q]
 
   const int n = a.n;
   const size_t plane = size_t(n) * n;
   const int tid = threadIdx.x;
   const int wave = tid / 64, lane = tid % 64;
-  const int comp = tid / kCols;  // uniform per wave
-  const int cid = tid % kCols, tx = cid % kTX, ty = cid / kTX;
-  const int i0 = blockIdx.x * kTX, j0 = blockIdx.y * kTY;
+  const int comp = blockIdx.x % 3;
+  const int tx = tid % kTX, ty = tid / kTX;
+  const int i0 = (blockIdx.x / 3) * kTX, j0 = blockIdx.y * kTY;
   const int t0 = blockIdx.z * a.zchunk;
   const int t1 = min(n, t0 + a.zchunk);
   const int i = i0 + tx, j = j0 + ty;
+  const int nfc = CT.nf[comp], npc = CT.np[comp];
+  const int planec = nfc * FPL;
 
   // x band rows of this thread's output column (registers, or LDS for the
   // residual stages)
@@ -187,18 +212,32 @@ __global__ __launch_bounds__(kRhsThreads) void rhs_kernel(RhsArgs<TC> a,
       for (int d = 0; d < W; ++d) xb[op][d] = (i < n) ? band[(size_t(op) * n + i) * W + d] : TC(0);
   }
 
-  // Offsets of this thread's staged values within a plane (-1: outside the
-  // patch, staged as zero) and the field they come from.
-  int goff[NLD], gfld[NLD];
+  // y band rows of the tile and z weights of the chunk's input planes (read
+  // by every lane: LDS broadcasts instead of scalar loads in the plane loop)
+  const int kbeg = max(t0 - P, 0), kend = min(t1 + P, n);  // input planes to read
+  for (int idx = tid; idx < 4 * kTY * W; idx += kRhsThreads) {
+    const int op = idx / (kTY * W), rem = idx % (kTY * W), yy = rem / W, d = rem % W;
+    sYB[idx] = band[(size_t(op) * n + min(j0 + yy, n - 1)) * W + d];
+  }
+  for (int idx = tid; idx < (kend - kbeg) * 4 * W; idx += kRhsThreads) {
+    const int kk = idx / (4 * W), rem = idx % (4 * W), op = rem / W, q = rem % W;
+    sZW[idx] = zw[(size_t(op) * n + kbeg + kk) * W + q];
+  }
+
+  // Sources of this thread's staged values: field pointer and offset within
+  // a plane (-1: outside the patch or past the component's fields, staged
+  // as zero).
+  int goff[NLD];
+  const TI* gsrc[NLD];
 #pragma unroll
   for (int u = 0; u < NLD; ++u) {
     const int idx = tid + u * kRhsThreads;
     goff[u] = -1;
-    gfld[u] = 0;
-    if (idx < PLANE) {
-      const int f = idx / (HY * HX), rem = idx % (HY * HX), yy = rem / HX, xx = rem % HX;
+    gsrc[u] = nullptr;
+    if (idx < planec) {
+      const int f = idx / FPL, rem = idx % FPL, yy = rem / HX, xx = rem % HX;
       const int gi = i0 - P + xx, gj = j0 - P + yy;
-      gfld[u] = f;
+      gsrc[u] = static_cast<const TI*>(a.f[CT.field[comp][f]]);
       if (gi >= 0 && gi < n && gj >= 0 && gj < n) goff[u] = gi + n * gj;
     }
   }
@@ -206,8 +245,7 @@ __global__ __launch_bounds__(kRhsThreads) void rhs_kernel(RhsArgs<TC> a,
 #pragma unroll
     for (int u = 0; u < NLD; ++u) {
       v[u] = TC(0);
-      if (goff[u] >= 0)
-        v[u] = TC(static_cast<const TI*>(a.f[gfld[u]])[size_t(goff[u]) + plane * size_t(k)]);
+      if (goff[u] >= 0) v[u] = TC(gsrc[u][size_t(goff[u]) + plane * size_t(k)]);
     }
   };
 
@@ -226,19 +264,27 @@ __global__ __launch_bounds__(kRhsThreads) void rhs_kernel(RhsArgs<TC> a,
            exp(-(s / a.src.width) * (s / a.src.width));
   }
 
-  const int kbeg = max(t0 - P, 0), kend = min(t1 + P, n);  // input planes to read
   // ring of kPrefetch planes in registers: pre[0] is the next plane to stage
   TC pre[kPrefetch][NLD];
 #pragma unroll
   for (int b = 0; b < kPrefetch; ++b)
     if (kbeg + b < kend) load_plane(kbeg + b, pre[b]);
   for (int k = t0 - P; k < t1 + P; ++k) {
+    // coefficients of the output plane finished in this iteration, loaded
+    // before this iteration's plane prefetch so that waiting for them never
+    // waits for the prefetch
+    const int te = k - P;
+    const bool wr = te >= t0 && te < t1 && i < n && j < n;
+    const size_t o = i + size_t(n) * j + plane * te;
+    TC cf[kE ? 3 : 1];
+#pragma unroll
+    for (int q = 0; q < (kE ? 3 : 1); ++q) cf[q] = wr ? a.coef[q][o] : TC(0);
     if (k >= kbeg && k < kend) {
       __syncthreads();  // the previous plane's passes are done with sF / sG
 #pragma unroll
       for (int u = 0; u < NLD; ++u) {
         const int idx = tid + u * kRhsThreads;
-        if (idx < PLANE) sF[idx] = pre[0][u];
+        if (idx < planec) sF[idx] = pre[0][u];
       }
 #pragma unroll
       for (int b = 0; b + 1 < kPrefetch; ++b)
@@ -246,31 +292,30 @@ __global__ __launch_bounds__(kRhsThreads) void rhs_kernel(RhsArgs<TC> a,
         for (int u = 0; u < NLD; ++u) pre[b][u] = pre[b + 1][u];
       if (k + kPrefetch < kend) load_plane(k + kPrefetch, pre[kPrefetch - 1]);
       __syncthreads();
-      // y pass: wave w handles pairs w, w + NWAVES, ...; lane = staged x column
-      static_for<NP>([&](auto pc) {
-        constexpr int pr = decltype(pc)::value;
-        constexpr int f = PT.field[pr], yop = PT.yop[pr];
-        if (wave == pr % NWAVES && lane < HX) {
+      // y pass: wave w handles the component's pairs w, w + NWAVES, ...;
+      // lane = staged x column
+      for (int pr = wave; pr < npc; pr += NWAVES) {
+        const int f = CT.pslot[comp][pr], yop = CT.pyop[comp][pr];
+        if (lane < HX) {
           TC col[HY];
 #pragma unroll
           for (int m = 0; m < HY; ++m) col[m] = sF[(f * HY + m) * HX + lane];
 #pragma unroll
           for (int yy = 0; yy < kTY; ++yy) {
-            const int gj = min(j0 + yy, n - 1);  // rows past the patch are never written
-            const TC* yb = band + (size_t(yop) * n + gj) * W;
+            const TC* yb = sYB + (yop * kTY + yy) * W;  // rows past the patch: never written
             TC s = TC(0);
 #pragma unroll
             for (int d = 0; d < W; ++d) s += yb[d] * col[yy + d];
             sG[(pr * kTY + yy) * HX + lane] = s;
           }
         }
-      });
+      }
       __syncthreads();
-      const TC* zk = zw + size_t(k) * W;
+      const TC* zk = sZW + (k - kbeg) * 4 * W;
       static_for<NT>([&](auto ic) {
         constexpr int it = decltype(ic)::value;
         constexpr Term tm = get_term<STAGE>(it);
-        constexpr int pr = PT.of_term[it];
+        constexpr int pr = CT.term_pair[it];
         if (tm.out == comp) {
           TC v = TC(0);
 #pragma unroll
@@ -279,20 +324,18 @@ __global__ __launch_bounds__(kRhsThreads) void rhs_kernel(RhsArgs<TC> a,
             v += xw * sG[(pr * kTY + ty) * HX + tx + d];
           }
           if (tm.sign < 0) v = -v;
-          const TC* zq = zk + size_t(tm.z) * n * W;
+          const TC* zq = zk + tm.z * W;
 #pragma unroll
           for (int q = 0; q < W; ++q) acc[tm.grp][q] += zq[q] * v;
         }
       });
     }
-    const int te = k - P;
     if (te >= t0 && te < t1) {
       if (i < n && j < n) {
-        const size_t o = i + size_t(n) * j + plane * te;
         const bool bi = (i == 0 || i == n - 1), bj = (j == 0 || j == n - 1),
                    bk = (te == 0 || te == n - 1);
         if (kE) {
-          const TC g = a.coef[0][o], b = a.coef[1][o], al = a.coef[2][o];
+          const TC g = cf[0], b = cf[1], al = cf[kE ? 2 : 0];
           TC v = g * acc[0][0] + b * acc[1][0] + al * acc[2][0];
           if (NG == 4) v += acc[NG - 1][0];
           if (comp == a.src.comp) {
@@ -304,7 +347,7 @@ __global__ __launch_bounds__(kRhsThreads) void rhs_kernel(RhsArgs<TC> a,
           const bool bnd = (comp == 0) ? (bj || bk) : (comp == 1) ? (bi || bk) : (bi || bj);
           static_cast<TO*>(a.out[comp])[o] = bnd ? TO(0) : TO(v);
         } else {
-          const TC v = acc[0][0] + a.coef[0][o] * acc[1][0];
+          const TC v = acc[0][0] + cf[0] * acc[1][0];
           // H_c is constrained on the faces normal to axis c
           const bool bnd = (comp == 0) ? bi : (comp == 1) ? bj : bk;
           static_cast<TO*>(a.out[comp])[o] = bnd ? TO(0) : TO(v);
@@ -842,11 +885,11 @@ hipError_t set_lds(K kernel, size_t bytes) {
 template <typename TI, typename TC, typename TO, int P, int STAGE>
 hipError_t launch_rhs_t(const RhsArgs<TC>& a, hipStream_t s) {
   auto k = rhs_kernel<TI, TC, TO, P, STAGE>;
-  const size_t lds = rhs_lds_bytes<TC, P, STAGE>();
+  const size_t lds = rhs_lds_bytes<TC, P, STAGE>(a.zchunk);
   hipError_t e = set_lds(k, lds);
   if (e != hipSuccess) return e;
   const int n = a.n;
-  dim3 grid((n + kTX - 1) / kTX, (n + kTY - 1) / kTY, (n + a.zchunk - 1) / a.zchunk);
+  dim3 grid(3 * ((n + kTX - 1) / kTX), (n + kTY - 1) / kTY, (n + a.zchunk - 1) / a.zchunk);
   hipLaunchKernelGGL(k, grid, dim3(kRhsThreads), lds, s, a, a.band, a.zw);
   return hipGetLastError();
 }
