@@ -46,6 +46,9 @@ struct adi_ctx {
   size_t esz = 8;          // bytes per field element
   hipStream_t stream = nullptr;
   hipStream_t cap = nullptr;
+  hipStream_t side = nullptr;        // second branch of a step: x-line sweeps beside y/z
+  std::vector<hipEvent_t> fork_ev;   // fork / join events of the branches
+  size_t fork_idx = 0;
   std::string err;
 
   std::vector<double> eps, mu, sig;
@@ -289,18 +292,33 @@ void axis_order(int kindH, int sub, int c, int order[3]) {
     if (a != m) order[k++] = a;
 }
 
+hipError_t next_event(adi_ctx* c, hipEvent_t* e) {
+  if (c->fork_idx == c->fork_ev.size()) {
+    hipEvent_t ev;
+    hipError_t err = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (err != hipSuccess) return err;
+    c->fork_ev.push_back(ev);
+  }
+  *e = c->fork_ev[c->fork_idx++];
+  return hipSuccess;
+}
+
 // Enqueue the three rounds of 1D solves of one stage on the three components
 // of `buf` (in place).  If `final_out` is given, the last solve of each
 // component writes final_out + solution instead (refine-mode correction).
+// Within a round the x-line launch and the y/z-line launch touch different
+// components: outside the profiling pass the x launch runs on a second
+// branch (the side stream, forked from and joined back into s).
 template <typename T>
 hipError_t enqueue_solves(adi_ctx* c, int kindH, int sub, void* buf, void* final_out,
                           hipStream_t s) {
   int order[3][3];
   for (int ci = 0; ci < 3; ++ci) axis_order(kindH, sub, ci, order[ci]);
   for (int r = 0; r < 3; ++r) {
+    SweepArgs grp[2]{};
+    int nd[2] = {0, 0};
     for (int xgroup = 1; xgroup >= 0; --xgroup) {
-      SweepArgs a{};
-      int nd = 0;
+      SweepArgs& a = grp[xgroup];
       for (int ci = 0; ci < 3; ++ci) {
         const int ax = order[ci][r];
         if ((ax == 0) != (xgroup == 1)) continue;
@@ -311,18 +329,38 @@ hipError_t enqueue_solves(adi_ctx* c, int kindH, int sub, void* buf, void* final
           out = comp(final_out, ci, c);
           acc = out;
         }
-        a.d[nd++] = desc_for(c, kindH, sub, ci, ax, in, out, acc);
+        a.d[nd[xgroup]++] = desc_for(c, kindH, sub, ci, ax, in, out, acc);
       }
-      if (nd == 0) continue;
       a.n = c->n;
       a.nlines = c->n * c->n;
       a.xaxis = xgroup;
       a.tick_t = nullptr;
       int nmod = 0;
-      for (int q = 0; q < nd; ++q) nmod += a.d[q].modified;
+      for (int q = 0; q < nd[xgroup]; ++q) nmod += a.d[q].modified;
       a.spike = (c->spike_ok && nmod == 0) ? 1 : 0;
-      hipError_t e = timed(c, s, xgroup ? kKindSweepX : kKindSweepYZ, nd, nmod,
-                           [&] { return launch_sweep<T>(c->p, nd, a, s); });
+    }
+    const bool branch = nd[0] > 0 && nd[1] > 0 && !c->profiling && c->side;
+    hipEvent_t ev = nullptr;
+    if (branch) {
+      hipError_t e = next_event(c, &ev);
+      if (e == hipSuccess) e = hipEventRecord(ev, s);
+      if (e == hipSuccess) e = hipStreamWaitEvent(c->side, ev, 0);
+      if (e != hipSuccess) return e;
+    }
+    for (int xgroup = 1; xgroup >= 0; --xgroup) {
+      if (nd[xgroup] == 0) continue;
+      const SweepArgs& a = grp[xgroup];
+      int nmod = 0;
+      for (int q = 0; q < nd[xgroup]; ++q) nmod += a.d[q].modified;
+      hipStream_t ls = (branch && xgroup == 1) ? c->side : s;
+      hipError_t e = timed(c, ls, xgroup ? kKindSweepX : kKindSweepYZ, nd[xgroup], nmod,
+                           [&] { return launch_sweep<T>(c->p, nd[xgroup], a, ls); });
+      if (e != hipSuccess) return e;
+    }
+    if (branch) {
+      hipError_t e = next_event(c, &ev);
+      if (e == hipSuccess) e = hipEventRecord(ev, c->side);
+      if (e == hipSuccess) e = hipStreamWaitEvent(s, ev, 0);
       if (e != hipSuccess) return e;
     }
   }
@@ -424,6 +462,7 @@ void drop_graph(adi_ctx* c) {
 int capture(adi_ctx* c) {
   drop_graph(c);
   c->launch_idx = 0;
+  c->fork_idx = 0;
   HIPCHK(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeRelaxed));
   hipError_t e = enqueue_step(c, c->cap);
   hipGraph_t g = nullptr;
@@ -444,6 +483,7 @@ bool finite_all(const double* v, size_t n) {
 int ensure_stream(adi_ctx* c) {
   if (c->cap) return ADI_OK;
   HIPCHK(c, hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+  HIPCHK(c, hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
   return ADI_OK;
 }
 
@@ -859,6 +899,8 @@ void adi_destroy(adi_ctx* c) {
   if (c->cl_red) hipFree(c->cl_red);
   if (c->cl_flag) hipFree(c->cl_flag);
   if (c->cap) hipStreamDestroy(c->cap);
+  if (c->side) hipStreamDestroy(c->side);
+  for (hipEvent_t e : c->fork_ev) hipEventDestroy(e);
   delete c;
 }
 
@@ -912,6 +954,7 @@ int adi_solve(adi_ctx* c, int stage, int sub, double* inout) {
   do {
     std::vector<double> v(inout, inout + 3 * D);
     if ((st = upload(c, d, v)) != ADI_OK) break;
+    c->fork_idx = 0;
     hipError_t e = es == 8 ? enqueue_solves<double>(c, stage, sub, d, nullptr, c->cap)
                            : enqueue_solves<float>(c, stage, sub, d, nullptr, c->cap);
     if (e != hipSuccess || hipStreamSynchronize(c->cap) != hipSuccess) { st = fail(c, ADI_EHIP, "solve kernels"); break; }

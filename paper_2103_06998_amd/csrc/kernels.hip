@@ -136,14 +136,14 @@ constexpr int kPrefetch = 2;        // input planes loaded ahead of use
 template <int STAGE>
 constexpr bool xband_in_lds() { return StageInfo<STAGE>::NG == 4; }
 
-// LDS of one RHS block: staged plane, y-pass results, x band rows (residual
+// LDS of one RHS block: y-pass results (two buffers), x band rows (residual
 // stages), the y band rows of the tile and the z weights of the chunk's
 // input planes.
 template <typename TC, int P, int STAGE>
 size_t rhs_lds_bytes(int zchunk) {
-  constexpr int HX = kTX + 2 * P, HY = kTY + 2 * P, W = 2 * P + 1;
+  constexpr int HX = kTX + 2 * P, W = 2 * P + 1;
   constexpr CompTab CT = make_comp_tab<STAGE>();
-  return sizeof(TC) * (size_t(CT.maxnf) * HY * HX + size_t(CT.maxnp) * kTY * HX +
+  return sizeof(TC) * (2 * size_t(CT.maxnp) * kTY * HX +
                        (xband_in_lds<STAGE>() ? 4 * kTX * W : 0) + size_t(4) * kTY * W +
                        size_t(zchunk + 2 * P) * 4 * W);
 }
@@ -152,16 +152,16 @@ size_t rhs_lds_bytes(int zchunk) {
 // Block = one output component of a kTX x kTY tile of (x, y) output columns
 // and a chunk of z planes (blockIdx.x = 3 * tile + component, so the three
 // components of a tile run side by side and share its inputs in L2).  Input
-// planes are marched along z: each plane of every field the component reads
-// is staged (with a p-halo in x and y) in LDS, the next planes are loaded
-// into registers meanwhile.  The y operators are applied by one wave per
-// (field, operator) pair, each lane producing a column of kTY values from
-// 2p + kTY staged values; the x operators are applied per output column with
-// the thread's band rows in registers, and each result is scattered into a
-// register queue of 2p+1 pending output planes with the z operator's
-// weights.  When the oldest pending plane is complete it is scaled by the
-// per-row coefficients and written.  TI: input type, TC: arithmetic type,
-// TO: output type.
+// planes are marched along z.  The y operators are applied by one wave per
+// (field, operator) pair of the component: lane = x column of the tile with
+// its p-halo, holding the 2p + kTY values of its column (loaded straight
+// from global memory kPrefetch planes ahead) and producing kTY values into
+// LDS (double buffered, so one barrier per plane suffices).  The x operators
+// are then applied per output column with the thread's band rows in
+// registers, and each result is scattered into a register queue of 2p+1
+// pending output planes with the z operator's weights.  When the oldest
+// pending plane is complete it is scaled by the per-row coefficients and
+// written.  TI: input type, TC: arithmetic type, TO: output type.
 template <typename TI, typename TC, typename TO, int P, int STAGE>
 __global__ __launch_bounds__(kRhsThreads) void rhs_kernel(RhsArgs<TC> a,
                                                           const TC* __restrict__ band,
@@ -170,17 +170,16 @@ __global__ __launch_bounds__(kRhsThreads) void rhs_kernel(RhsArgs<TC> a,
   constexpr int NT = StageInfo<STAGE>::NT, NG = StageInfo<STAGE>::NG;
   constexpr CompTab CT = make_comp_tab<STAGE>();
   constexpr bool kE = !(STAGE == kStageH1 || STAGE == kStageH2);
-  constexpr int FPL = HY * HX;                                  // staged values per field
-  constexpr int PLANE = CT.maxnf * FPL;                         // staged values per plane
-  constexpr int NLD = (PLANE + kRhsThreads - 1) / kRhsThreads;  // per thread
   constexpr int NWAVES = kRhsThreads / 64;
-  static_assert(HX <= 64, "one lane per staged x column in the y pass");
+  constexpr int NPW = (CT.maxnp + NWAVES - 1) / NWAVES;  // pairs per wave
+  constexpr int NPF = NPW > 1 ? 1 : kPrefetch;           // planes in flight per pair
+  constexpr int GSZ = CT.maxnp * kTY * HX;                // one y-pass buffer
+  static_assert(HX <= 64, "one lane per x column in the y pass");
 
   extern __shared__ __align__(16) unsigned char smem[];
-  TC* sF = reinterpret_cast<TC*>(smem);
-  TC* sG = sF + PLANE;
+  TC* sG = reinterpret_cast<TC*>(smem);  // [2][pair][yy][x]
   constexpr bool kXL = xband_in_lds<STAGE>();
-  TC* sBX = sG + CT.maxnp * kTY * HX;       // x band rows (residual stages only)
+  TC* sBX = sG + 2 * GSZ;                   // x band rows (residual stages only)
   TC* sYB = sBX + (kXL ? 4 * kTX * W : 0);  // y band rows [op][yy][d] of the tile
   TC* sZW = sYB + 4 * kTY * W;              // z weights [plane - kbeg][op][q]
 
@@ -194,8 +193,7 @@ __global__ __launch_bounds__(kRhsThreads) void rhs_kernel(RhsArgs<TC> a,
   const int t0 = blockIdx.z * a.zchunk;
   const int t1 = min(n, t0 + a.zchunk);
   const int i = i0 + tx, j = j0 + ty;
-  const int nfc = CT.nf[comp], npc = CT.np[comp];
-  const int planec = nfc * FPL;
+  const int npc = CT.np[comp];
 
   // x band rows of this thread's output column (registers, or LDS for the
   // residual stages)
@@ -224,28 +222,30 @@ __global__ __launch_bounds__(kRhsThreads) void rhs_kernel(RhsArgs<TC> a,
     sZW[idx] = zw[(size_t(op) * n + kbeg + kk) * W + q];
   }
 
-  // Sources of this thread's staged values: field pointer and offset within
-  // a plane (-1: outside the patch or past the component's fields, staged
-  // as zero).
-  int goff[NLD];
-  const TI* gsrc[NLD];
+  // This wave's (field, y operator) pairs and this lane's column: x = i0 - P
+  // + lane, rows y = j0 - P + m (m < HY); values outside the patch are zero.
+  const int gi = i0 - P + lane;
+  const bool colok = lane < HX && gi >= 0 && gi < n;
+  const TI* psrc[NPW];
+  int pyop[NPW], pid[NPW];
 #pragma unroll
-  for (int u = 0; u < NLD; ++u) {
-    const int idx = tid + u * kRhsThreads;
-    goff[u] = -1;
-    gsrc[u] = nullptr;
-    if (idx < planec) {
-      const int f = idx / FPL, rem = idx % FPL, yy = rem / HX, xx = rem % HX;
-      const int gi = i0 - P + xx, gj = j0 - P + yy;
-      gsrc[u] = static_cast<const TI*>(a.f[CT.field[comp][f]]);
-      if (gi >= 0 && gi < n && gj >= 0 && gj < n) goff[u] = gi + n * gj;
-    }
+  for (int q = 0; q < NPW; ++q) {
+    const int pr = wave + q * NWAVES;
+    pid[q] = pr;
+    const bool on = pr < npc;
+    pyop[q] = on ? CT.pyop[comp][pr] : 0;
+    psrc[q] = on && colok ? static_cast<const TI*>(a.f[CT.field[comp][CT.pslot[comp][pr]]])
+                          : nullptr;
   }
-  auto load_plane = [&](int k, TC (&v)[NLD]) {
+  int rowlo = P - j0, rowhi = n - j0 + P;  // rows m in [rowlo, rowhi) are inside the patch
+  rowlo = max(rowlo, 0);
+  rowhi = min(rowhi, HY);
+  const size_t cbase = size_t(gi) + size_t(n) * (j0 - P);  // only used when colok
+  auto load_col = [&](int k, int q, TI (&v)[HY]) {
 #pragma unroll
-    for (int u = 0; u < NLD; ++u) {
-      v[u] = TC(0);
-      if (goff[u] >= 0) v[u] = TC(gsrc[u][size_t(goff[u]) + plane * size_t(k)]);
+    for (int m = 0; m < HY; ++m) {
+      v[m] = TI(0);
+      if (psrc[q] && m >= rowlo && m < rowhi) v[m] = psrc[q][cbase + size_t(m) * n + plane * size_t(k)];
     }
   };
 
@@ -264,11 +264,14 @@ __global__ __launch_bounds__(kRhsThreads) void rhs_kernel(RhsArgs<TC> a,
            exp(-(s / a.src.width) * (s / a.src.width));
   }
 
-  // ring of kPrefetch planes in registers: pre[0] is the next plane to stage
-  TC pre[kPrefetch][NLD];
+  // ring of NPF planes of this lane's columns (input type): pre[q][0] is the next
+  TI pre[NPW][NPF][HY];
 #pragma unroll
-  for (int b = 0; b < kPrefetch; ++b)
-    if (kbeg + b < kend) load_plane(kbeg + b, pre[b]);
+  for (int q = 0; q < NPW; ++q)
+#pragma unroll
+    for (int b = 0; b < NPF; ++b)
+      if (kbeg + b < kend) load_col(kbeg + b, q, pre[q][b]);
+  __syncthreads();  // band rows and z weights staged
   for (int k = t0 - P; k < t1 + P; ++k) {
     // coefficients of the output plane finished in this iteration, loaded
     // before this iteration's plane prefetch so that waiting for them never
@@ -280,35 +283,28 @@ __global__ __launch_bounds__(kRhsThreads) void rhs_kernel(RhsArgs<TC> a,
 #pragma unroll
     for (int q = 0; q < (kE ? 3 : 1); ++q) cf[q] = wr ? a.coef[q][o] : TC(0);
     if (k >= kbeg && k < kend) {
-      __syncthreads();  // the previous plane's passes are done with sF / sG
+      TC* G = sG + ((k - kbeg) & 1) * GSZ;
+      // y pass from registers
 #pragma unroll
-      for (int u = 0; u < NLD; ++u) {
-        const int idx = tid + u * kRhsThreads;
-        if (idx < planec) sF[idx] = pre[0][u];
-      }
-#pragma unroll
-      for (int b = 0; b + 1 < kPrefetch; ++b)
-#pragma unroll
-        for (int u = 0; u < NLD; ++u) pre[b][u] = pre[b + 1][u];
-      if (k + kPrefetch < kend) load_plane(k + kPrefetch, pre[kPrefetch - 1]);
-      __syncthreads();
-      // y pass: wave w handles the component's pairs w, w + NWAVES, ...;
-      // lane = staged x column
-      for (int pr = wave; pr < npc; pr += NWAVES) {
-        const int f = CT.pslot[comp][pr], yop = CT.pyop[comp][pr];
-        if (lane < HX) {
-          TC col[HY];
-#pragma unroll
-          for (int m = 0; m < HY; ++m) col[m] = sF[(f * HY + m) * HX + lane];
+      for (int q = 0; q < NPW; ++q) {
+        if (pid[q] < npc && lane < HX) {
+          const TC* yb0 = sYB + pyop[q] * kTY * W;
 #pragma unroll
           for (int yy = 0; yy < kTY; ++yy) {
-            const TC* yb = sYB + (yop * kTY + yy) * W;  // rows past the patch: never written
             TC s = TC(0);
 #pragma unroll
-            for (int d = 0; d < W; ++d) s += yb[d] * col[yy + d];
-            sG[(pr * kTY + yy) * HX + lane] = s;
+            for (int d = 0; d < W; ++d) s += yb0[yy * W + d] * TC(pre[q][0][yy + d]);
+            G[(pid[q] * kTY + yy) * HX + lane] = s;
           }
         }
+      }
+#pragma unroll
+      for (int q = 0; q < NPW; ++q) {
+#pragma unroll
+        for (int b = 0; b + 1 < NPF; ++b)
+#pragma unroll
+          for (int m = 0; m < HY; ++m) pre[q][b][m] = pre[q][b + 1][m];
+        if (k + NPF < kend) load_col(k + NPF, q, pre[q][NPF - 1]);
       }
       __syncthreads();
       const TC* zk = sZW + (k - kbeg) * 4 * W;
@@ -321,7 +317,7 @@ __global__ __launch_bounds__(kRhsThreads) void rhs_kernel(RhsArgs<TC> a,
 #pragma unroll
           for (int d = 0; d < W; ++d) {
             const TC xw = kXL ? sBX[(tm.x * kTX + tx) * W + d] : xb[kXL ? 0 : tm.x][d];
-            v += xw * sG[(pr * kTY + ty) * HX + tx + d];
+            v += xw * G[(pr * kTY + ty) * HX + tx + d];
           }
           if (tm.sign < 0) v = -v;
           const TC* zq = zk + tm.z * W;
