@@ -382,7 +382,9 @@ __device__ __forceinline__ void stage_batched(T* dst, const T* __restrict__ src,
 // in LDS, and the tile is written back.  Lines along y and z are loaded with
 // consecutive lanes on consecutive x (coalesced); lines along x are contiguous
 // in memory and are transposed through LDS.
-constexpr int kLoadCH = 32;  // rows per lane loaded together
+// rows per lane loaded together (float tiles: every row of a 64-row chunk in flight)
+template <typename T>
+struct SweepLoadRows { static constexpr int value = sizeof(T) == 8 ? 32 : 64; };
 constexpr int kCH = 8;       // rows per compute chunk of the LDS part
 
 // Rows of a line kept in registers (the rest in LDS): float64 tiles would
@@ -412,6 +414,7 @@ __host__ __device__ inline int sweep_buf_rows(int n, bool xax, int rr) {
 // per-line factors are read as [((k*n) + r)*nlines + l].
 template <typename T, int P, bool XAX, bool MOD>
 __global__ __launch_bounds__(64) void sweep_kernel(SweepArgs a) {
+  constexpr int kLoadCH = SweepLoadRows<T>::value;
   constexpr int PIT = sweep_pitch(XAX);
   constexpr int kRR = SweepRegRows<T>::value;
   constexpr int kRA = kRR > 0 ? kRR : 1;  // register array extent
@@ -549,47 +552,26 @@ __global__ __launch_bounds__(64) void sweep_kernel(SweepArgs a) {
     h[0] = s;
     yr[r] = s;
   }
-  // ---- forward, LDS rows
-  for (int r0 = kRR; r0 < n; r0 += kCH) {
-    T v[kCH], f[kCH][P];
+  // ---- forward, LDS rows.  Per-line factors (global memory) of the next
+  // chunk are loaded while the current chunk is computed.
+  {
+    T f[kCH][P];
+    auto load_f = [&](int r0, T (&g)[kCH][P]) {
 #pragma unroll
-    for (int c = 0; c < kCH; ++c) {
-      const int rf = min(r0 + c, n - 1);
-      v[c] = buf[(rf - kRR) * PIT + lane];
+      for (int c = 0; c < kCH; ++c)
 #pragma unroll
-      for (int k = 0; k < P; ++k) f[c][k] = fL(rf, k);
-    }
+        for (int k = 0; k < P; ++k) g[c][k] = fL(min(r0 + c, n - 1), k);
+    };
+    if (kRR < n) load_f(kRR, f);
+    for (int r0 = kRR; r0 < n; r0 += kCH) {
+      T fn[kCH][P];
+      if (MOD && r0 + kCH < n) load_f(r0 + kCH, fn);
+      T v[kCH];
 #pragma unroll
-    for (int c = 0; c < kCH; ++c) {
-      T s = v[c];
+      for (int c = 0; c < kCH; ++c) v[c] = buf[(min(r0 + c, n - 1) - kRR) * PIT + lane];
 #pragma unroll
-      for (int k = P - 1; k >= 0; --k) s -= f[c][k] * h[k];
-#pragma unroll
-      for (int k = P - 1; k > 0; --k) h[k] = h[k - 1];
-      h[0] = s;
-      v[c] = s;
-    }
-#pragma unroll
-    for (int c = 0; c < kCH; ++c)
-      if (r0 + c < n) buf[(r0 + c - kRR) * PIT + lane] = v[c];
-  }
-  // ---- backward, LDS rows (from the last row down to kRR)
-#pragma unroll
-  for (int k = 0; k < P; ++k) h[k] = T(0);
-  for (int r0 = n - 1; r0 >= kRR; r0 -= kCH) {
-    T v[kCH], f[kCH][P], d[kCH];
-#pragma unroll
-    for (int c = 0; c < kCH; ++c) {
-      const int rf = max(r0 - c, kRR);
-      v[c] = buf[(rf - kRR) * PIT + lane];
-#pragma unroll
-      for (int k = 0; k < P; ++k) f[c][k] = fU(rf, k);
-      d[c] = fD(rf);
-    }
-#pragma unroll
-    for (int c = 0; c < kCH; ++c) {
-      if (r0 - c >= kRR) {  // uniform
-        T s = d[c] * v[c];
+      for (int c = 0; c < kCH; ++c) {
+        T s = v[c];
 #pragma unroll
         for (int k = P - 1; k >= 0; --k) s -= f[c][k] * h[k];
 #pragma unroll
@@ -597,10 +579,70 @@ __global__ __launch_bounds__(64) void sweep_kernel(SweepArgs a) {
         h[0] = s;
         v[c] = s;
       }
-    }
 #pragma unroll
-    for (int c = 0; c < kCH; ++c)
-      if (r0 - c >= kRR) buf[(r0 - c - kRR) * PIT + lane] = v[c];
+      for (int c = 0; c < kCH; ++c)
+        if (r0 + c < n) buf[(r0 + c - kRR) * PIT + lane] = v[c];
+      if (r0 + kCH < n) {
+        if (MOD) {
+#pragma unroll
+          for (int c = 0; c < kCH; ++c)
+#pragma unroll
+            for (int k = 0; k < P; ++k) f[c][k] = fn[c][k];
+        } else {
+          load_f(r0 + kCH, f);
+        }
+      }
+    }
+  }
+  // ---- backward, LDS rows (from the last row down to kRR)
+#pragma unroll
+  for (int k = 0; k < P; ++k) h[k] = T(0);
+  {
+    T f[kCH][P], d[kCH];
+    auto load_f = [&](int r0, T (&g)[kCH][P], T (&e)[kCH]) {
+#pragma unroll
+      for (int c = 0; c < kCH; ++c) {
+        const int rf = max(r0 - c, kRR);
+#pragma unroll
+        for (int k = 0; k < P; ++k) g[c][k] = fU(rf, k);
+        e[c] = fD(rf);
+      }
+    };
+    if (n - 1 >= kRR) load_f(n - 1, f, d);
+    for (int r0 = n - 1; r0 >= kRR; r0 -= kCH) {
+      T fn[kCH][P], dn[kCH];
+      if (MOD && r0 - kCH >= kRR) load_f(r0 - kCH, fn, dn);
+      T v[kCH];
+#pragma unroll
+      for (int c = 0; c < kCH; ++c) v[c] = buf[(max(r0 - c, kRR) - kRR) * PIT + lane];
+#pragma unroll
+      for (int c = 0; c < kCH; ++c) {
+        if (r0 - c >= kRR) {  // uniform
+          T s = d[c] * v[c];
+#pragma unroll
+          for (int k = P - 1; k >= 0; --k) s -= f[c][k] * h[k];
+#pragma unroll
+          for (int k = P - 1; k > 0; --k) h[k] = h[k - 1];
+          h[0] = s;
+          v[c] = s;
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < kCH; ++c)
+        if (r0 - c >= kRR) buf[(r0 - c - kRR) * PIT + lane] = v[c];
+      if (r0 - kCH >= kRR) {
+        if (MOD) {
+#pragma unroll
+          for (int c = 0; c < kCH; ++c) {
+#pragma unroll
+            for (int k = 0; k < P; ++k) f[c][k] = fn[c][k];
+            d[c] = dn[c];
+          }
+        } else {
+          load_f(r0 - kCH, f, d);
+        }
+      }
+    }
   }
   // ---- backward, register rows (padding rows r >= n are skipped)
 #pragma unroll
