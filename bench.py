@@ -41,33 +41,35 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(launch, D, wbytes):
+def algorithmic_bytes(launch, D, wbytes, refine=False):
     """Bytes a launch must move at minimum (each array read or written once).
 
-    rhs_E:  6 fields + alpha, beta, gamma read, 3 right-hand sides written;
+    rhs_E:  6 fields + alpha, beta, gamma read, 3 right-hand sides written
+            (refine mode: float32 fields, float64 coefficients, the float64
+            right-hand sides and their float32 copies written);
     rhs_H:  9 fields (H, E old, E new) + delta read, 3 written;
-    residual64 (refine mode): 9 float32 fields + 3 float64 coefficients read,
-            3 float32 residuals written;
+    residual64 (refine mode): float32 solution x, float64 right-hand sides b
+            and alpha read, float32 residuals b - P x written;
     sweeps: per component the right-hand side read and the solution written,
             plus the per-row coefficient on a material-modified axis.
     """
     k = launch["kind"]
     if k == "rhs_E":
-        return 12 * D * wbytes
+        return D * (6 * 4 + 3 * 8 + 3 * 8 + 3 * 4) if refine else 12 * D * wbytes
     if k == "rhs_H":
         return 13 * D * wbytes
     if k == "residual64":
-        return D * (12 * 4 + 3 * 8)
+        return D * (3 * 4 + 3 * 8 + 8 + 3 * 4)
     return D * wbytes * (2 * launch["ncomp"] + launch["nmod"])
 
 
-def summarize(launches, D, wbytes):
+def summarize(launches, D, wbytes, refine):
     by = {}
     for L in launches:
         b = by.setdefault(L["kind"], dict(total_ms=0.0, launches=0, bytes=0.0))
         b["total_ms"] += L["ms"]
         b["launches"] += 1
-        b["bytes"] += algorithmic_bytes(L, D, wbytes)
+        b["bytes"] += algorithmic_bytes(L, D, wbytes, refine)
     for k, b in by.items():
         b["avg_ms"] = b["total_ms"] / b["launches"]
         b["achieved_GBs"] = b["bytes"] / (b["total_ms"] * 1e-3) / 1e9
@@ -115,7 +117,8 @@ def run_gpu(precision, w, steps, warmup):
     s.profile(max(5, min(steps, 50)))
     launches = s.profile_read()
     wbytes = 8 if precision == "fp64" else 4
-    kinds = summarize(launches, D, wbytes)
+    refine = precision != "fp64"
+    kinds = summarize(launches, D, wbytes, refine)
     EH, t = s.get_fields()
     finite = bool(np.isfinite(EH).all())
     s.close()
@@ -131,7 +134,7 @@ def run_gpu(precision, w, steps, warmup):
         "traffic": traffic_from_profiles(dom, precision),
         "bytes_per_launch": int(per_launch_bytes), "avg_launch_ms": round(b["avg_ms"], 5),
     }
-    step_bytes = sum(algorithmic_bytes(L, D, wbytes) for L in launches)
+    step_bytes = sum(algorithmic_bytes(L, D, wbytes, refine) for L in launches)
     kernel_ms = sum(L["ms"] for L in launches)
     return dict(value=value, ms_per_step=ms_step, roofline=roofline, finite=finite,
                 kernels={k: {kk: (round(vv, 5) if isinstance(vv, float) else vv)

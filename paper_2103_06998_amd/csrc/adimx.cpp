@@ -79,6 +79,7 @@ struct adi_ctx {
   double* minratio = nullptr;
   double* d_t = nullptr;
   float* R32 = nullptr;     // residual scratch (refine mode), 3 D
+  double* b64 = nullptr;    // float64 E right-hand sides (refine mode), 3 D
 
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -157,6 +158,7 @@ size_t layout(adi_ctx* c, unsigned char* base) {
   c->minratio = reinterpret_cast<double*>(take(size_t(n) * n * 8));
   c->d_t = reinterpret_cast<double*>(take(8));
   c->R32 = c->refine() ? reinterpret_cast<float*>(take(3 * D * 4)) : nullptr;
+  c->b64 = c->refine() ? reinterpret_cast<double*>(take(3 * D * 8)) : nullptr;
   return cur + 256;
 }
 
@@ -381,32 +383,49 @@ hipError_t enqueue_step_t(adi_ctx* c, hipStream_t s) {
       const void* f[6] = {comp(Ein, 0, c), comp(Ein, 1, c), comp(Ein, 2, c),
                           comp(Hin, 0, c), comp(Hin, 1, c), comp(Hin, 2, c)};
       void* out[3] = {comp(Eout, 0, c), comp(Eout, 1, c), comp(Eout, 2, c)};
-      RhsArgs<T> a = rhs_args<T>(c, f, 6, out, 0, sub);
-      hipError_t e = timed(c, s, kKindRhsE, 3, 0, [&] {
-        return launch_rhs<T>(sub == 1 ? kStageE1 : kStageE2, c->p, a, s);
-      });
-      if (e != hipSuccess) return e;
-      e = enqueue_solves<T>(c, 0, sub, Eout, nullptr, s);
-      if (e != hipSuccess) return e;
-      if (c->refine()) {
-        const void* fr[9] = {f[0], f[1], f[2], f[3], f[4], f[5],
-                             comp(Eout, 0, c), comp(Eout, 1, c), comp(Eout, 2, c)};
-        void* rout[3] = {c->R32, c->R32 + c->D, c->R32 + 2 * c->D};
+      hipError_t e;
+      if (!c->refine()) {
+        RhsArgs<T> a = rhs_args<T>(c, f, 6, out, 0, sub);
+        e = timed(c, s, kKindRhsE, 3, 0, [&] {
+          return launch_rhs<T>(sub == 1 ? kStageE1 : kStageE2, c->p, a, s);
+        });
+        if (e != hipSuccess) return e;
+        e = enqueue_solves<T>(c, 0, sub, Eout, nullptr, s);
+        if (e != hipSuccess) return e;
+      } else {
+        // float64 right-hand sides b (kept for the residual) and their
+        // float32 copies for the float32 solve
+        RhsArgs<double> a = rhs_args<double>(c, f, 6, out, 0, sub);
+        for (int i = 0; i < 3; ++i) {
+          a.out[i] = c->b64 + size_t(i) * c->D;
+          a.out2[i] = out[i];
+        }
+        a.coef[0] = c->coef64[2];
+        a.coef[1] = c->coef64[1];
+        a.coef[2] = c->coef64[0];
+        a.band = c->band64;
+        a.zw = c->zw64;
+        e = timed(c, s, kKindRhsE, 3, 0, [&] {
+          return launch_rhs_e64(sub == 1 ? kStageE1 : kStageE2, c->p, a, s);
+        });
+        if (e != hipSuccess) return e;
+        e = enqueue_solves<float>(c, 0, sub, Eout, nullptr, s);
+        if (e != hipSuccess) return e;
+        // residual r = b - P x in float64 (stored float32), one correction solve
         RhsArgs<double> r{};
-        for (int i = 0; i < 9; ++i) r.f[i] = fr[i];
-        for (int i = 0; i < 3; ++i) r.out[i] = rout[i];
-        r.coef[0] = c->coef64[2];
-        r.coef[1] = c->coef64[1];
-        r.coef[2] = c->coef64[0];
+        for (int i = 0; i < 3; ++i) {
+          r.f[i] = comp(Eout, i, c);
+          r.bin[i] = c->b64 + size_t(i) * c->D;
+          r.out[i] = c->R32 + size_t(i) * c->D;
+        }
+        r.coef[2] = c->coef64[0];  // alpha
         r.band = c->band64;
         r.zw = c->zw64;
         r.n = c->n;
         r.zchunk = pick_zchunk(c->n);
-        r.src = c->src;
         r.tnow = c->d_t;
-        r.frac_dt = (sub == 1 ? 0.25 : 0.75) * c->dt;
         e = timed(c, s, kKindResidual, 3, 0, [&] {
-          return launch_residual(sub == 1 ? kStageR1 : kStageR2, c->p, r, s);
+          return launch_residual(sub == 1 ? kStageQ1 : kStageQ2, c->p, r, s);
         });
         if (e != hipSuccess) return e;
         e = enqueue_solves<float>(c, 0, sub, c->R32, Eout, s);

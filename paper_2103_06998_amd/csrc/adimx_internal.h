@@ -57,6 +57,8 @@ enum RhsStage : int {
   kStageH2 = 3,   // H right-hand sides, substep 2 (eq. discrete4)
   kStageR1 = 4,   // E residual b - P x of substep 1 (float64 correction)
   kStageR2 = 5,   // E residual of substep 2
+  kStageQ1 = 6,   // E residual b - P x of substep 1 from a given float64 b
+  kStageQ2 = 7,   // the same for substep 2
 };
 
 struct SourceArgs {
@@ -71,7 +73,9 @@ struct RhsArgs {
   const void* f[9];       // input fields (E stage: E1..E3,H1..H3; H stage: H1..H3,
                           // E_old1..3, E_new1..3; residual: E1..E3,H1..H3,X1..X3)
   void* out[3];           // T (or float for the residual in refine mode)
-  const T* coef[3];       // E: gamma, beta, alpha ; H: delta
+  void* out2[3];          // optional second copy of the E outputs, float32
+  const double* bin[3];   // Q stages: the float64 right-hand sides b
+  const T* coef[3];       // E: gamma, beta, alpha ; H: delta; Q: -, -, alpha
   const T* band;          // [op][r][2p+1], op 0 = M, 1 = A, 2 = B, 3 = S
   const T* zw;            // [op][k][2p+1]: weight of input plane k on output plane
                           // k - p + q (band entry Z[k-p+q][k], zero outside)
@@ -119,6 +123,9 @@ struct FactorArgs {
 template <typename T>
 hipError_t launch_rhs(int stage, int p, const RhsArgs<T>& a, hipStream_t stream);
 hipError_t launch_residual(int stage, int p, const RhsArgs<double>& a, hipStream_t stream);
+// E right-hand sides in float64 arithmetic from float32 fields: float64
+// outputs (out) and their float32 copies (out2).
+hipError_t launch_rhs_e64(int stage, int p, const RhsArgs<double>& a, hipStream_t stream);
 template <typename T>
 hipError_t launch_sweep(int p, int ndesc, const SweepArgs& a, hipStream_t stream);
 hipError_t launch_factor(int p, const FactorArgs& a, hipStream_t stream);

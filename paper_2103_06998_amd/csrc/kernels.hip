@@ -32,6 +32,8 @@ constexpr int OM = 0, OA = 1, OB = 2, OS = 3;
 //    discrete4: RH1 = MMM H1 + d MMA E2' - d MAM E3'', ... (sign of scheme1d)
 //  Residual stages (fields E, H, X = float32 solution; groups gamma, beta,
 //    alpha, 1): the E right-hand side minus (M..M) X minus alpha (..S..) X.
+//  Q stages (fields X; groups alpha, 1): a given float64 right-hand side b
+//    minus (M..M) X minus alpha (..S..) X.
 template <int STAGE>
 struct StageInfo;
 template <> struct StageInfo<kStageE1> { static constexpr int NT = 12, NF = 6, NG = 3; };
@@ -40,6 +42,8 @@ template <> struct StageInfo<kStageH1> { static constexpr int NT = 9, NF = 9, NG
 template <> struct StageInfo<kStageH2> { static constexpr int NT = 9, NF = 9, NG = 2; };
 template <> struct StageInfo<kStageR1> { static constexpr int NT = 18, NF = 9, NG = 4; };
 template <> struct StageInfo<kStageR2> { static constexpr int NT = 18, NF = 9, NG = 4; };
+template <> struct StageInfo<kStageQ1> { static constexpr int NT = 6, NF = 3, NG = 4; };
+template <> struct StageInfo<kStageQ2> { static constexpr int NT = 6, NF = 3, NG = 4; };
 
 template <int STAGE>
 __host__ __device__ constexpr Term get_term(int i) {
@@ -70,6 +74,11 @@ __host__ __device__ constexpr Term get_term(int i) {
       {2, 0, +1, 2, OM, OM, OM}, {2, 1, +1, 3, OM, OA, OM}, {2, 1, -1, 7, OA, OM, OM}};
   if (STAGE == kStageH1) return h_sub1[i];
   if (STAGE == kStageH2) return h_sub2[i];
+  if (STAGE == kStageQ1 || STAGE == kStageQ2) {  // the product-operator terms alone, on X1..X3
+    Term t = STAGE == kStageQ1 ? px_sub1[i] : px_sub2[i];
+    t.field -= 6;
+    return t;
+  }
   if (i < 9) return curl_and_mass[i];
   const bool sub2 = (STAGE == kStageE2 || STAGE == kStageR2);
   if (i < 12) return sub2 ? r_sub2[i - 9] : r_sub1[i - 9];
@@ -170,6 +179,7 @@ __global__ __launch_bounds__(kRhsThreads) void rhs_kernel(RhsArgs<TC> a,
   constexpr int NT = StageInfo<STAGE>::NT, NG = StageInfo<STAGE>::NG;
   constexpr CompTab CT = make_comp_tab<STAGE>();
   constexpr bool kE = !(STAGE == kStageH1 || STAGE == kStageH2);
+  constexpr bool kQ = STAGE == kStageQ1 || STAGE == kStageQ2;
   constexpr int NWAVES = kRhsThreads / 64;
   constexpr int NPW = (CT.maxnp + NWAVES - 1) / NWAVES;  // pairs per wave
   constexpr int NPF = NPW > 1 ? 1 : kPrefetch;           // planes in flight per pair
@@ -281,7 +291,11 @@ __global__ __launch_bounds__(kRhsThreads) void rhs_kernel(RhsArgs<TC> a,
     const size_t o = i + size_t(n) * j + plane * te;
     TC cf[kE ? 3 : 1];
 #pragma unroll
-    for (int q = 0; q < (kE ? 3 : 1); ++q) cf[q] = wr ? a.coef[q][o] : TC(0);
+    for (int q = 0; q < (kE ? 3 : 1); ++q) {
+      if (kQ && q == 0) cf[q] = wr ? TC(a.bin[comp][o]) : TC(0);
+      else if (kQ && q == 1) cf[q] = TC(0);
+      else cf[q] = wr ? a.coef[q][o] : TC(0);
+    }
     if (k >= kbeg && k < kend) {
       TC* G = sG + ((k - kbeg) & 1) * GSZ;
       // y pass from registers
@@ -332,9 +346,9 @@ __global__ __launch_bounds__(kRhsThreads) void rhs_kernel(RhsArgs<TC> a,
                    bk = (te == 0 || te == n - 1);
         if (kE) {
           const TC g = cf[0], b = cf[1], al = cf[kE ? 2 : 0];
-          TC v = g * acc[0][0] + b * acc[1][0] + al * acc[2][0];
+          TC v = kQ ? g + al * acc[2][0] : g * acc[0][0] + b * acc[1][0] + al * acc[2][0];
           if (NG == 4) v += acc[NG - 1][0];
-          if (comp == a.src.comp) {
+          if (!kQ && comp == a.src.comp) {
             const int ri = i - a.src.first[0], rj = j - a.src.first[1], rk = te - a.src.first[2];
             if (ri >= 0 && ri <= P && rj >= 0 && rj <= P && rk >= 0 && rk <= P)
               v -= b * TC(jsrc * (a.src.bz[rk] * a.src.by[rj] * a.src.bx[ri]));
@@ -342,6 +356,7 @@ __global__ __launch_bounds__(kRhsThreads) void rhs_kernel(RhsArgs<TC> a,
           // E_c is constrained on the faces normal to the two other axes
           const bool bnd = (comp == 0) ? (bj || bk) : (comp == 1) ? (bi || bk) : (bi || bj);
           static_cast<TO*>(a.out[comp])[o] = bnd ? TO(0) : TO(v);
+          if (a.out2[comp]) static_cast<float*>(a.out2[comp])[o] = bnd ? 0.0f : float(v);
         } else {
           const TC v = acc[0][0] + cf[0] * acc[1][0];
           // H_c is constrained on the faces normal to axis c
@@ -946,8 +961,17 @@ hipError_t launch_rhs_p(int stage, const RhsArgs<TC>& a, hipStream_t s) {
 template <int P>
 hipError_t launch_res_p(int stage, const RhsArgs<double>& a, hipStream_t s) {
   switch (stage) {
-    case kStageR1: return launch_rhs_t<float, double, float, P, kStageR1>(a, s);
-    case kStageR2: return launch_rhs_t<float, double, float, P, kStageR2>(a, s);
+    case kStageQ1: return launch_rhs_t<float, double, float, P, kStageQ1>(a, s);
+    case kStageQ2: return launch_rhs_t<float, double, float, P, kStageQ2>(a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int P>
+hipError_t launch_e64_p(int stage, const RhsArgs<double>& a, hipStream_t s) {
+  switch (stage) {
+    case kStageE1: return launch_rhs_t<float, double, double, P, kStageE1>(a, s);
+    case kStageE2: return launch_rhs_t<float, double, double, P, kStageE2>(a, s);
   }
   return hipErrorInvalidValue;
 }
@@ -1024,6 +1048,16 @@ hipError_t launch_rhs(int stage, int p, const RhsArgs<T>& a, hipStream_t s) {
 }
 template hipError_t launch_rhs<double>(int, int, const RhsArgs<double>&, hipStream_t);
 template hipError_t launch_rhs<float>(int, int, const RhsArgs<float>&, hipStream_t);
+
+hipError_t launch_rhs_e64(int stage, int p, const RhsArgs<double>& a, hipStream_t s) {
+  switch (p) {
+    case 1: return launch_e64_p<1>(stage, a, s);
+    case 2: return launch_e64_p<2>(stage, a, s);
+    case 3: return launch_e64_p<3>(stage, a, s);
+    case 4: return launch_e64_p<4>(stage, a, s);
+  }
+  return hipErrorInvalidValue;
+}
 
 // float64 residual of the float32 E solve: inputs float32, arithmetic float64,
 // output float32 (the residual is small; float32 keeps ~7 digits of it).
