@@ -150,10 +150,12 @@ size_t layout(adi_ctx* c, unsigned char* base) {
     const int q = 2 * P * (kSpikeS - 1);
     for (int v = 0; v < 2; ++v) c->spk[v] = take((size_t(n) * (4 * P + 1) + size_t(q) * q) * es);
   }
+  // per-line factors in blocks of 64 lines (the line count padded to 64)
+  const size_t nlpad = (size_t(n) * n + 63) / 64 * 64;
   for (int s = 0; s < 6; ++s) {
-    c->mL[s] = take(size_t(P) * D * es);
-    c->mU[s] = take(size_t(P) * D * es);
-    c->mD[s] = take(D * es);
+    c->mL[s] = take(size_t(P) * n * nlpad * es);
+    c->mU[s] = take(size_t(P) * n * nlpad * es);
+    c->mD[s] = take(size_t(n) * nlpad * es);
   }
   c->minratio = reinterpret_cast<double*>(take(size_t(n) * n * 8));
   c->d_t = reinterpret_cast<double*>(take(8));

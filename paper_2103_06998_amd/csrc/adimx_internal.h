@@ -91,9 +91,10 @@ struct SweepDesc {
   void* in;               // right-hand sides (T)
   void* out;              // solution (T); may equal in
   const void* acc;        // if non-null, out = solution + acc (element-wise)
-  const void* L;          // factors; shared: [r*P + k-1], modified: [((k-1)*n + r)*nlines + l]
+  const void* L;          // factors; shared: [r*P + k-1],
+                          // modified: [((l/64 * n + r) * P + k-1) * 64 + l%64]
   const void* U;          // D * U (pre-scaled upper factor), same layout as L
-  const void* D;          // inverse diagonal; shared: [r], modified: [r*nlines + l]
+  const void* D;          // inverse diagonal; shared: [r], modified: [(l/64 * n + r) * 64 + l%64]
   const void* spk;        // shared factors only: partitioned-solve data (L, DU, D, V, W
                           // as [r*P + k] / [r], then R, q x q), or null
   int modified;           // 0 = shared factors, 1 = per-line factors

@@ -426,7 +426,7 @@ __host__ __device__ inline int sweep_buf_rows(int n, bool xax, int rr) {
 // Forward: y_r = b_r - sum_k L[r][k] y_{r-1-k}; backward:
 // x_r = D_r y_r - sum_k DU[r][k] x_{r+1+k}, DU = D * U pre-scaled, so each row
 // adds one dependent FMA.  Shared factors [r*P + k] / [r] are staged in LDS;
-// per-line factors are read as [((k*n) + r)*nlines + l].
+// per-line factors are read as [((l/64 * n + r) * P + k) * 64 + l%64].
 template <typename T, int P, bool XAX, bool MOD>
 __global__ __launch_bounds__(64) void sweep_kernel(SweepArgs a) {
   constexpr int kLoadCH = SweepLoadRows<T>::value;
@@ -535,20 +535,22 @@ __global__ __launch_bounds__(64) void sweep_kernel(SweepArgs a) {
     __syncthreads();  // shared factors
   }
 
-  const size_t fstride = size_t(n) * nl;
   const T* __restrict__ Lm = static_cast<const T*>(ds.L);
   const T* __restrict__ Um = static_cast<const T*>(ds.U);
   const T* __restrict__ Dm = static_cast<const T*>(ds.D);
+  // per-line factors: [line / 64][row][k][line % 64], so that a wave's
+  // factors are one contiguous stream
+  const size_t fb = size_t(blockIdx.x) * n;
   auto fL = [&](int r, int k) -> T {
-    if (MOD) return Lm[(size_t(k) * n + r) * nl + lc];
+    if (MOD) return Lm[((fb + r) * P + k) * 64 + lane];
     return sfac[r * P + k];
   };
   auto fU = [&](int r, int k) -> T {
-    if (MOD) return Um[(size_t(k) * n + r) * nl + lc];
+    if (MOD) return Um[((fb + r) * P + k) * 64 + lane];
     return sfac[n * P + r * P + k];
   };
   auto fD = [&](int r) -> T {
-    if (MOD) return Dm[size_t(r) * nl + lc];
+    if (MOD) return Dm[(fb + r) * 64 + lane];
     return sfac[2 * n * P + r];
   };
 
@@ -859,7 +861,6 @@ __global__ __launch_bounds__(64) void factor_kernel(FactorArgs a) {
   if (a.axis == 0) { lbase = size_t(l) * n; rstride = 1; }
   else if (a.axis == 1) { lbase = size_t(l % n) + size_t(l / n) * n2; rstride = n; }
   else { lbase = l; rstride = n2; }
-  const size_t fstride = size_t(n) * nl;
 
   double up[P + 1][P + 1];  // up[m][c] = U_{i-m, i-m+c}
 #pragma unroll
@@ -894,9 +895,10 @@ __global__ __launch_bounds__(64) void factor_kernel(FactorArgs a) {
       ur[c] = s;
     }
     const double dinv = 1.0 / ur[0];
+    const size_t ob = size_t(l >> 6) * n + i;  // per-line factors: [line / 64][row][k][line % 64]
 #pragma unroll
     for (int m = 1; m <= P; ++m) {
-      const size_t o = size_t(m - 1) * fstride + size_t(i) * nl + l;
+      const size_t o = (ob * P + (m - 1)) * 64 + (l & 63);
       const double du = dinv * ur[m];  // pre-scaled for the backward substitution
       if (a.L64) {
         a.L64[o] = Lr[m];
@@ -907,8 +909,8 @@ __global__ __launch_bounds__(64) void factor_kernel(FactorArgs a) {
         a.U32[o] = float(du);
       }
     }
-    if (a.D64) a.D64[size_t(i) * nl + l] = dinv;
-    if (a.D32) a.D32[size_t(i) * nl + l] = float(dinv);
+    if (a.D64) a.D64[ob * 64 + (l & 63)] = dinv;
+    if (a.D32) a.D32[ob * 64 + (l & 63)] = float(dinv);
     const double ratio = fabs(ur[0]) / fabs(A[P]);
     minr = ratio < minr ? ratio : minr;
 #pragma unroll
