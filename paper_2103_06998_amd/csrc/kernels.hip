@@ -759,9 +759,39 @@ __global__ __launch_bounds__(64 * kSpikeS) void spike_kernel(SweepArgs a) {
 
   // unconditional loads (rows past the segment repeat its last row) keep
   // every load of the segment in flight at once
+  // x lines (contiguous in memory) go through a per-wave LDS tile of 8 rows
+  // x 64 lines: lanes read runs of 8 consecutive values (coalesced) and each
+  // lane then takes its own line's rows.  LDS operations of one wave execute
+  // in order, so the tile needs no barrier.
+  T* xt = gex + Q * 64 + seg * (8 * 65);
+  const int l0 = blockIdx.x * 64;
   T y[MR];
+  if (XAX) {
 #pragma unroll
-  for (int r = 0; r < MR; ++r) y[r] = in[lbase + size_t(b0 + min(r, m - 1)) * rstride];
+    for (int c0 = 0; c0 < MR; c0 += 8) {
+      if (c0 < m) {  // uniform
+        T v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int e = lane + 64 * j, ln = e >> 3, rr = e & 7;
+          v[j] = in[size_t(min(l0 + ln, nl - 1)) * n + b0 + min(c0 + rr, m - 1)];
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int e = lane + 64 * j;
+          xt[(e & 7) * 65 + (e >> 3)] = v[j];
+        }
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int rr = 0; rr < 8; ++rr)
+          if (c0 + rr < MR) y[c0 + rr] = xt[rr * 65 + lane];
+        __builtin_amdgcn_wave_barrier();
+      }
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < MR; ++r) y[r] = in[lbase + size_t(b0 + min(r, m - 1)) * rstride];
+  }
   stage_batched<T, 64 * S>(sf, static_cast<const T*>(ds.spk), nf, tid);
   __syncthreads();  // factors staged
 
@@ -837,9 +867,39 @@ __global__ __launch_bounds__(64 * kSpikeS) void spike_kernel(SweepArgs a) {
       T x = y[r];
 #pragma unroll
       for (int k = 0; k < P; ++k) x -= sV[g * P + k] * tn[k] + sW[g * P + k] * up[k];
-      const size_t o = lbase + size_t(g) * rstride;
-      if (accp) x += accp[o];
-      if (act) out[o] = x;
+      y[r] = x;
+    }
+  }
+  if (XAX) {
+#pragma unroll
+    for (int c0 = 0; c0 < MR; c0 += 8) {
+      if (c0 < m) {  // uniform
+#pragma unroll
+        for (int rr = 0; rr < 8; ++rr)
+          if (c0 + rr < MR) xt[rr * 65 + lane] = y[c0 + rr];
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int e = lane + 64 * j, ln = e >> 3, rr = e & 7;
+          if (l0 + ln < nl && c0 + rr < m) {
+            const size_t o = size_t(l0 + ln) * n + b0 + c0 + rr;
+            T x = xt[rr * 65 + ln];
+            if (accp) x += accp[o];
+            out[o] = x;
+          }
+        }
+        __builtin_amdgcn_wave_barrier();
+      }
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < MR; ++r) {
+      if (r < m) {
+        const size_t o = lbase + size_t(b0 + r) * rstride;
+        T x = y[r];
+        if (accp) x += accp[o];
+        if (act) out[o] = x;
+      }
     }
   }
   if (a.tick_t && blockIdx.x == 0 && blockIdx.y == 0 && tid == 0) *a.tick_t += a.tick_dt;
@@ -1004,7 +1064,8 @@ hipError_t launch_sweep_k(int ndesc, const SweepArgs& a, hipStream_t s) {
 template <typename T, int P, bool XAX, int MR>
 hipError_t launch_spike_k(int ndesc, const SweepArgs& a, hipStream_t s) {
   constexpr int Q = 2 * P * (kSpikeS - 1);
-  const size_t lds = (size_t(a.n) * (4 * P + 1) + Q * Q + size_t(Q) * 64) * sizeof(T);
+  const size_t lds = (size_t(a.n) * (4 * P + 1) + Q * Q + size_t(Q) * 64 +
+                      (XAX ? size_t(kSpikeS) * 8 * 65 : 0)) * sizeof(T);
   dim3 grid((a.nlines + 63) / 64, ndesc);
   auto k = spike_kernel<T, P, XAX, MR>;
   hipError_t e = set_lds(k, lds);
