@@ -137,6 +137,7 @@ __device__ __forceinline__ void static_for(F&& f) {
 }
 
 constexpr int kTX = 32, kTY = 8, kCols = kTX * kTY;
+constexpr int kXcds = 8;  // MI355X: 8 accelerator complex dies, one L2 each
 constexpr int kRhsThreads = kCols;  // one block per (tile, output component)
 constexpr int kPrefetch = 2;        // input planes loaded ahead of use
 
@@ -159,8 +160,8 @@ size_t rhs_lds_bytes(int zchunk) {
 
 // ------------------------------------------------------------ RHS kernel
 // Block = one output component of a kTX x kTY tile of (x, y) output columns
-// and a chunk of z planes (blockIdx.x = 3 * tile + component, so the three
-// components of a tile run side by side and share its inputs in L2).  Input
+// and a chunk of z planes, mapped so that the three components of a tile and
+// its x neighbours run on one XCD and share their inputs in its L2.  Input
 // planes are marched along z.  The y operators are applied by one wave per
 // (field, operator) pair of the component: lane = x column of the tile with
 // its p-halo, holding the 2p + kTY values of its column (loaded straight
@@ -197,10 +198,29 @@ __global__ __launch_bounds__(kRhsThreads) void rhs_kernel(RhsArgs<TC> a,
   const size_t plane = size_t(n) * n;
   const int tid = threadIdx.x;
   const int wave = tid / 64, lane = tid % 64;
-  const int comp = blockIdx.x % 3;
+  // Work item of this block.  Workgroups are dealt to the 8 XCDs (each with
+  // its own L2) round robin by linear id; item w = ((zc * nty + ty) * ntx +
+  // tx) * 3 + component is assigned so that each XCD runs a contiguous range
+  // of items: the three components of a tile and its x neighbours share
+  // their inputs in one L2.
+  int comp, bx, by, bz;
+  {
+    const int ntx = gridDim.x / 3, nty = gridDim.y;
+    const int total = gridDim.x * gridDim.y * gridDim.z;
+    const int b = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+    const int xcd = b % kXcds, k = b / kXcds;
+    const int q = total / kXcds, r = total % kXcds;
+    int w = xcd * q + min(xcd, r) + k;
+    comp = w % 3;
+    w /= 3;
+    bx = w % ntx;
+    w /= ntx;
+    by = w % nty;
+    bz = w / nty;
+  }
   const int tx = tid % kTX, ty = tid / kTX;
-  const int i0 = (blockIdx.x / 3) * kTX, j0 = blockIdx.y * kTY;
-  const int t0 = blockIdx.z * a.zchunk;
+  const int i0 = bx * kTX, j0 = by * kTY;
+  const int t0 = bz * a.zchunk;
   const int t1 = min(n, t0 + a.zchunk);
   const int i = i0 + tx, j = j0 + ty;
   const int npc = CT.np[comp];
