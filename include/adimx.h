@@ -52,7 +52,11 @@ enum {
                           correction per E solve                              */
 };
 
-enum { ADI_MAP_GREVILLE = 0 };
+enum {
+  ADI_MAP_GREVILLE = 0,    /* each DOF takes the voxel containing its Greville point  */
+  ADI_MAP_BSPLINE_AVG = 1  /* each DOF takes the voxel values averaged with the
+                              weights of its test function B_r B_s B_t               */
+};
 
 /*
  * Create a context for an N x N x N element patch of degree p (1 <= p <= 4,
@@ -77,10 +81,13 @@ int adi_bind_workspace(adi_ctx* ctx, void* dev_ptr, size_t bytes);
 /*
  * Material given as a voxel map (vx, vy, vz voxels, x fastest, float64):
  * relative permittivity, relative permeability and the non-dimensional
- * conductivity sigma_nd = Z0 L sigma.  Each degree of freedom takes the
- * voxel containing the Greville point of its test function (material is
- * attached to test functions, eq. dupa1abcdefg and the text around it).
- * EINVAL if eps <= 0, mu <= 0, sigma < 0 or a value is not finite.
+ * conductivity sigma_nd = Z0 L sigma.  Material is attached to test
+ * functions (eq. dupa1abcdefg and the text around it): with map_mode
+ * ADI_MAP_GREVILLE each degree of freedom takes the voxel containing the
+ * Greville point of its test function; with ADI_MAP_BSPLINE_AVG it takes the
+ * voxel values averaged with the weights of its test function (integrals of
+ * B_r B_s B_t over the voxels, normalised).  EINVAL if eps <= 0, mu <= 0,
+ * sigma < 0, a value is not finite or map_mode is unknown.
  */
 int adi_set_material(adi_ctx* ctx, const double* eps_r, const double* mu_r,
                      const double* sigma_nd, int vx, int vy, int vz, int map_mode);
@@ -110,6 +117,17 @@ int adi_set_source(adi_ctx* ctx, const double xs[3], int comp, double amp, doubl
 
 /* Upload a state (6 n^3 float64, layout above) and set the time t. */
 int adi_set_fields(adi_ctx* ctx, const double* EH, double t);
+
+/*
+ * Local time step per test function (section "Incorporating non-regular
+ * material data": like eps and mu, tau may be replaced by tau-hat for a test
+ * function): tau holds n^3 values (layout as the fields, finite, >= 0) that
+ * replace dt in the row coefficients alpha, beta, gamma, delta of that
+ * degree of freedom; the time levels (source time, time advance) stay those
+ * of dt.  tau = NULL restores dt everywhere.  Takes effect at the next
+ * adi_factor.
+ */
+int adi_set_local_dt(adi_ctx* ctx, const double* tau);
 
 /*
  * Enqueue nsteps full time steps on the context's stream and return without

@@ -127,6 +127,42 @@ def source_time(t, src) -> float:
     return float(np.sin(2.0 * np.pi * src.f0 * s) * np.exp(-(s / src.width) ** 2))
 
 
+def voxel_weights(N: int, p: int, V: int) -> np.ndarray:
+    """W[i, v] = (integral of B_i over voxel v) / (integral of B_i over [0, 1]).
+
+    Each voxel [v/V, (v+1)/V] is split at the knots inside it and every piece
+    is integrated with (p + 1)-point Gauss-Legendre (exact for the degree-p
+    pieces)."""
+    knots = bspline.open_uniform_knots(N, p)
+    n = N + p
+    g, w = np.polynomial.legendre.leggauss(p + 1)
+    W = np.zeros((n, V))
+    inner = np.unique(knots)
+    for v in range(V):
+        a, b = v / V, (v + 1) / V
+        cuts = np.concatenate([[a], inner[(inner > a) & (inner < b)], [b]])
+        for lo, hi in zip(cuts[:-1], cuts[1:]):
+            x = 0.5 * (lo + hi) + 0.5 * (hi - lo) * g
+            W[:, v] += (0.5 * (hi - lo) * w) @ bspline.basis(knots, p, x)
+    return W / W.sum(axis=1, keepdims=True)
+
+
+def average_material(N: int, p: int, eps_vox, mu_vox, sig_vox):
+    """Per-DOF (eps, mu, sigma) as the B-spline-weighted average of a voxel map:
+    the material of test function B_r B_s B_t is the mean of the voxel values
+    weighted by that function (a smoother alternative to Greville sampling of
+    the test-function-wise material of the section on non-regular material).
+    Voxel arrays are (Vz, Vy, Vx)."""
+    Vz, Vy, Vx = np.shape(eps_vox)
+    wx, wy, wz = voxel_weights(N, p, Vx), voxel_weights(N, p, Vy), voxel_weights(N, p, Vz)
+    def avg(m):
+        m = np.asarray(m, float)                  # (Vz, Vy, Vx)
+        m = np.einsum("ia,cba->cbi", wx, m)       # x
+        m = np.einsum("jb,cbi->cji", wy, m)       # y
+        return np.einsum("kc,cji->kji", wz, m)    # z
+    return avg(eps_vox), avg(mu_vox), avg(sig_vox)
+
+
 def sample_material(N: int, p: int, eps_vox, mu_vox, sig_vox):
     """Per-DOF (eps, mu, sigma) by Greville sampling of a voxel map (R4).
 
@@ -165,6 +201,11 @@ class Problem:
     sig: np.ndarray
     dt: float
     source: Optional[object] = None
+    # Local time step per test function (section on non-regular material
+    # data: tau may be replaced by tau-hat for test function rst like eps and
+    # mu): per-DOF array used in the row coefficients, or None for dt.  The
+    # time levels (source time, step count) stay those of dt.
+    local_dt: Optional[np.ndarray] = None
 
     def __post_init__(self):
         self.n = self.N + self.p
@@ -176,7 +217,9 @@ class Problem:
             raise ValueError("need eps > 0, mu > 0, sigma >= 0")
         self.M, self.S, self.A, self.B = gram.gram_matrices(self.N, self.p)
         self.ops = {"M": self.M, "A": self.A, "B": self.B}
-        self.coef = coefficients(self.eps, self.mu, self.sig, self.dt)
+        tau = self.dt if self.local_dt is None else \
+            np.broadcast_to(np.asarray(self.local_dt, float), shape).copy()
+        self.coef = coefficients(self.eps, self.mu, self.sig, tau)
         self.coef["one"] = np.ones(shape)
         self.knots = bspline.open_uniform_knots(self.N, self.p)
 
@@ -269,7 +312,14 @@ class Problem:
         return e
 
 
-def problem_from_voxels(N: int, p: int, material, dt: float, source=None) -> Problem:
-    """Problem with Greville-sampled voxel material (sigma non-dimensional)."""
-    eps, mu, sig = sample_material(N, p, material.eps_r, material.mu_r, material.sigma_nd)
+def problem_from_voxels(N: int, p: int, material, dt: float, source=None,
+                        mapping: str = "greville") -> Problem:
+    """Problem with voxel material (sigma non-dimensional) mapped to the test
+    functions by Greville sampling or by the B-spline-weighted average."""
+    if mapping == "greville":
+        eps, mu, sig = sample_material(N, p, material.eps_r, material.mu_r, material.sigma_nd)
+    elif mapping == "bspline_avg":
+        eps, mu, sig = average_material(N, p, material.eps_r, material.mu_r, material.sigma_nd)
+    else:
+        raise ValueError(mapping)
     return Problem(N, p, eps, mu, sig, dt, source)

@@ -52,6 +52,7 @@ struct adi_ctx {
   std::string err;
 
   std::vector<double> eps, mu, sig;
+  std::vector<double> tau;  // local time step per DOF (empty: dt everywhere)
   bool have_material = false;
   SourceArgs src;
   double src_xs[3] = {0.5, 0.5, 0.5};
@@ -596,13 +597,61 @@ int adi_set_material_dof(adi_ctx* c, const double* eps, const double* mu, const 
 int adi_set_material(adi_ctx* c, const double* eps_r, const double* mu_r, const double* sigma_nd,
                      int vx, int vy, int vz, int map_mode) {
   if (!c || !eps_r || !mu_r || !sigma_nd || vx < 1 || vy < 1 || vz < 1) return ADI_EINVAL;
-  if (map_mode != ADI_MAP_GREVILLE) return fail(c, ADI_EINVAL, "unknown material map mode");
+  if (map_mode != ADI_MAP_GREVILLE && map_mode != ADI_MAP_BSPLINE_AVG)
+    return fail(c, ADI_EINVAL, "unknown material map mode");
   const size_t V = size_t(vx) * vy * vz;
   for (size_t i = 0; i < V; ++i) {
     if (!std::isfinite(eps_r[i]) || !std::isfinite(mu_r[i]) || !std::isfinite(sigma_nd[i]))
       return fail(c, ADI_EINVAL, "material value not finite");
     if (!(eps_r[i] > 0.0) || !(mu_r[i] > 0.0) || sigma_nd[i] < 0.0)
       return fail(c, ADI_EINVAL, "need eps > 0, mu > 0, sigma >= 0");
+  }
+  if (map_mode == ADI_MAP_BSPLINE_AVG) {
+    // DOF (i,j,k) takes the voxel values averaged with the weights of its
+    // test function B_i B_j B_k, one axis at a time (x, then y, then z)
+    const int n = c->n;
+    const std::vector<double> wx = voxel_weights(c->N, c->p, vx), wy = voxel_weights(c->N, c->p, vy),
+                              wz = voxel_weights(c->N, c->p, vz);
+    auto avg = [&](const double* m, std::vector<double>& out) {
+      std::vector<double> a(size_t(vz) * vy * n, 0.0), b(size_t(vz) * n * n, 0.0);
+      for (int k = 0; k < vz; ++k)
+        for (int j = 0; j < vy; ++j) {
+          const double* row = m + (size_t(k) * vy + j) * vx;
+          double* o = a.data() + (size_t(k) * vy + j) * n;
+          for (int i = 0; i < n; ++i) {
+            const double* w = wx.data() + size_t(i) * vx;
+            double s = 0.0;
+            for (int v = 0; v < vx; ++v) s += w[v] * row[v];
+            o[i] = s;
+          }
+        }
+      for (int k = 0; k < vz; ++k)
+        for (int jj = 0; jj < n; ++jj) {
+          const double* w = wy.data() + size_t(jj) * vy;
+          double* o = b.data() + (size_t(k) * n + jj) * n;
+          for (int v = 0; v < vy; ++v) {
+            if (w[v] == 0.0) continue;
+            const double* src = a.data() + (size_t(k) * vy + v) * n;
+            for (int i = 0; i < n; ++i) o[i] += w[v] * src[i];
+          }
+        }
+      out.assign(c->D, 0.0);
+      for (int kk = 0; kk < n; ++kk) {
+        const double* w = wz.data() + size_t(kk) * vz;
+        double* o = out.data() + size_t(kk) * n * n;
+        for (int v = 0; v < vz; ++v) {
+          if (w[v] == 0.0) continue;
+          const double* src = b.data() + size_t(v) * n * n;
+          for (size_t q = 0; q < size_t(n) * n; ++q) o[q] += w[v] * src[q];
+        }
+      }
+    };
+    avg(eps_r, c->eps);
+    avg(mu_r, c->mu);
+    avg(sigma_nd, c->sig);
+    c->have_material = true;
+    c->factored = false;
+    return ADI_OK;
   }
   // Greville sampling: DOF (i,j,k) takes the voxel containing (xi_i, xi_j, xi_k).
   const std::vector<double> xi = greville(c->N, c->p);
@@ -627,6 +676,20 @@ int adi_set_material(adi_ctx* c, const double* eps_r, const double* mu_r, const 
         c->sig[o] = sigma_nd[v];
       }
   c->have_material = true;
+  c->factored = false;
+  return ADI_OK;
+}
+
+int adi_set_local_dt(adi_ctx* c, const double* tau) {
+  if (!c) return ADI_EINVAL;
+  if (!tau) {
+    c->tau.clear();
+  } else {
+    for (size_t i = 0; i < c->D; ++i)
+      if (!std::isfinite(tau[i]) || tau[i] < 0.0)
+        return fail(c, ADI_EINVAL, "local time steps must be finite and >= 0");
+    c->tau.assign(tau, tau + c->D);
+  }
   c->factored = false;
   return ADI_OK;
 }
@@ -737,13 +800,15 @@ int adi_factor(adi_ctx* c, double dt) {
   // gamma = (1-c)/(1+c), delta = dt/(2 mu)
   std::vector<double> co[4];
   for (auto& v : co) v.resize(D);
+  // (a local time step per test function replaces dt in its row)
   for (size_t i = 0; i < D; ++i) {
     const double e = c->eps[i], m = c->mu[i], s = c->sig[i];
-    const double cc = s * dt / (4.0 * e);
-    co[0][i] = dt * dt / (4.0 * e * m * (1.0 + cc));
-    co[1][i] = dt / (2.0 * e * (1.0 + cc));
+    const double tt = c->tau.empty() ? dt : c->tau[i];
+    const double cc = s * tt / (4.0 * e);
+    co[0][i] = tt * tt / (4.0 * e * m * (1.0 + cc));
+    co[1][i] = tt / (2.0 * e * (1.0 + cc));
     co[2][i] = (1.0 - cc) / (1.0 + cc);
-    co[3][i] = dt / (2.0 * m);
+    co[3][i] = tt / (2.0 * m);
   }
   for (int i = 0; i < 4; ++i) {
     if ((st = upload(c, c->coefT[i], co[i])) != ADI_OK) return st;

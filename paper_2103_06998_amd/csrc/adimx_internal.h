@@ -31,6 +31,8 @@ void apply_dirichlet(std::vector<double>& band, int n, int p);
 double band_lu(const std::vector<double>& band, int n, int p, std::vector<double>& L,
                std::vector<double>& Uoff, std::vector<double>& Uinv);
 std::vector<double> greville(int N, int p);
+// W[i*V + v]: share of the integral of B_i over [0, 1] that lies in voxel v.
+std::vector<double> voxel_weights(int N, int p, int V);
 
 // Partitioned (SPIKE) solve data of one shared banded matrix split into S
 // row segments [spike_boundary(n,S,i), spike_boundary(n,S,i+1)):

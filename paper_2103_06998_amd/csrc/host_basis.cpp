@@ -364,6 +364,41 @@ bool spike_prepare(const std::vector<double>& band, int n, int p, int S, SpikeDa
   return true;
 }
 
+std::vector<double> voxel_weights(int N, int p, int V) {
+  // Fraction of the integral of each B-spline over each voxel: pieces of
+  // the voxel between knots are integrated with (p+1)-point Gauss rules
+  // (exact on polynomial pieces), then every row is normalised.
+  const int n = N + p;
+  const std::vector<double> t = open_knots(N, p);
+  std::vector<double> gx, gw;
+  gauss_legendre(p + 1, gx, gw);
+  std::vector<double> W(size_t(n) * V, 0.0), vals(p + 1);
+  for (int v = 0; v < V; ++v) {
+    const double a = double(v) / V, b = double(v + 1) / V;
+    std::vector<double> cuts{a};
+    for (int e = 1; e < N; ++e) {
+      const double k = double(e) / N;
+      if (k > a && k < b) cuts.push_back(k);
+    }
+    cuts.push_back(b);
+    for (size_t c = 0; c + 1 < cuts.size(); ++c) {
+      const double lo = cuts[c], hi = cuts[c + 1], half = 0.5 * (hi - lo);
+      for (int g = 0; g <= p; ++g) {
+        const double x = 0.5 * (lo + hi) + half * gx[g];
+        const int span = find_span(t, p, n, x);
+        basis_on_span(t, p, span, x, vals.data(), nullptr);
+        for (int r = 0; r <= p; ++r) W[size_t(span - p + r) * V + v] += half * gw[g] * vals[r];
+      }
+    }
+  }
+  for (int i = 0; i < n; ++i) {
+    double s = 0.0;
+    for (int v = 0; v < V; ++v) s += W[size_t(i) * V + v];
+    for (int v = 0; v < V; ++v) W[size_t(i) * V + v] /= s;
+  }
+  return W;
+}
+
 std::vector<double> greville(int N, int p) {
   std::vector<double> t = open_knots(N, p), xi(N + p);
   for (int i = 0; i < N + p; ++i) {

@@ -72,12 +72,15 @@ class Solver:
             pass
 
     # -- setup ---------------------------------------------------------------
-    def set_material(self, eps_r, mu_r, sigma_nd):
-        """Voxel material map (arrays shaped (Vz, Vy, Vx)); Greville sampling."""
+    MAPS = {"greville": _lib.ADI_MAP_GREVILLE, "bspline_avg": _lib.ADI_MAP_BSPLINE_AVG}
+
+    def set_material(self, eps_r, mu_r, sigma_nd, mapping: str = "greville"):
+        """Voxel material map (arrays shaped (Vz, Vy, Vx)) attached to the test
+        functions by Greville sampling or the B-spline-weighted average."""
         e, m, s = (self._arr(v) for v in (eps_r, mu_r, sigma_nd))
         Vz, Vy, Vx = np.shape(eps_r)
         self._check(self.lib.adi_set_material(self.h, _lib.dptr(e), _lib.dptr(m), _lib.dptr(s),
-                                              Vx, Vy, Vz, _lib.ADI_MAP_GREVILLE))
+                                              Vx, Vy, Vz, self.MAPS[mapping]))
 
     def set_material_dof(self, eps, mu, sigma_nd):
         D = self.n ** 3
@@ -89,6 +92,14 @@ class Solver:
         x = self._arr(xs, 3)
         self._check(self.lib.adi_set_source(self.h, _lib.dptr(x), int(comp), float(amp),
                                             float(f0), float(t0), float(width)))
+
+    def set_local_dt(self, tau=None):
+        """Per-DOF local time step in the row coefficients (None: dt)."""
+        if tau is None:
+            self._check(self.lib.adi_set_local_dt(self.h, None))
+            return
+        a = self._arr(np.broadcast_to(np.asarray(tau, float), (self.n,) * 3), self.n ** 3)
+        self._check(self.lib.adi_set_local_dt(self.h, _lib.dptr(a)))
 
     def factor(self, dt: float):
         self._check(self.lib.adi_factor(self.h, float(dt)))

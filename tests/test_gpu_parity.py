@@ -241,3 +241,45 @@ def test_resume_equals_uninterrupted(Solver):
     s.step(3)
     resumed, t_res = s.get_fields()
     assert np.array_equal(full, resumed) and t_full == t_res
+
+
+@pytest.mark.parametrize("N,p,V", [(5, 2, 7), (12, 3, 20), (50, 2, 64)])
+def test_bspline_averaged_material_steps(Solver, N, p, V):
+    """B-spline-weighted material map: steps on the GPU against the oracle
+    stepping with the oracle's own averaged material."""
+    mat = workloads.blob_map(V, 40 + N)
+    src = workloads.DipoleSource(xs=(0.4, 0.55, 0.5), f0=2.0, t0=0.05, width=0.3)
+    dt = 0.5 / N
+    prob = maxwell.problem_from_voxels(N, p, mat, dt, src, mapping="bspline_avg")
+    s = Solver(N, p, "fp64")
+    s.set_material(mat.eps_r, mat.mu_r, mat.sigma_nd, mapping="bspline_avg")
+    s.set_source(src.xs, src.comp, src.amp, src.f0, src.t0, src.width)
+    s.factor(dt)
+    E, H = constrained_random_state(prob, 5)
+    s.set_fields(np.stack(E + H), 0.02)
+    s.step(2)
+    E, H, _ = prob.run(E, H, 0.02, 2)
+    got, _ = s.get_fields()
+    compare_state(got, E, H, TOL64, ("bspline_avg", N, p, V))
+
+
+@pytest.mark.parametrize("N,p", [(4, 2), (9, 3), (50, 2)])
+def test_local_time_step_steps(Solver, N, p):
+    """Per-test-function local time step: GPU steps against the oracle."""
+    eps, mu, sig, src = random_setup(N, p, seed=300 + N)
+    n = N + p
+    dt = 0.5 / N
+    tau = np.random.default_rng(N).uniform(0.2 * dt, 1.5 * dt, (n, n, n))
+    prob = maxwell.Problem(N, p, eps, mu, sig, dt, src, local_dt=tau)
+    s = Solver(N, p, "fp64")
+    s.set_material_dof(eps, mu, sig)
+    s.set_source(src.xs, src.comp, src.amp, src.f0, src.t0, src.width)
+    s.set_local_dt(tau)
+    s.factor(dt)
+    E, H = constrained_random_state(prob, 6)
+    s.set_fields(np.stack(E + H), 0.01)
+    s.step(2)
+    E, H, t = prob.run(E, H, 0.01, 2)
+    got, tg = s.get_fields()
+    assert tg == pytest.approx(t, rel=1e-14)
+    compare_state(got, E, H, TOL64, ("local dt", N, p))

@@ -117,20 +117,22 @@ def _free_mask(n, kind):
     return np.concatenate(masks)
 
 
-def _dense_step(N, p, eps, mu, sig, dt, src, E, H, t):
+def _dense_step(N, p, eps, mu, sig, dt, src, E, H, t, tau=None):
     """One step from the dense block systems; eps, mu, sig scalars or per-DOF
-    arrays (material attached to test functions = rows, reading R4/R5)."""
+    arrays (material attached to test functions = rows, reading R4/R5); tau
+    a per-row time step in the row coefficients (default dt)."""
     M, S, A, B = gram.gram_matrices(N, p)
     n = N + p
     K = _blocks(M, S, A, B)
     C = K["C1"] - K["C2"]
     full = lambda v: np.tile(np.broadcast_to(np.asarray(v, float), (n, n, n)).ravel(), 3)
     eps, mu, sig = full(eps), full(mu), full(sig)
-    c = sig * dt / (4 * eps)
-    a = dt * dt / (4 * eps * mu * (1 + c))
-    b = dt / (2 * eps * (1 + c))
+    tr = full(dt if tau is None else tau)
+    c = sig * tr / (4 * eps)
+    a = tr * tr / (4 * eps * mu * (1 + c))
+    b = tr / (2 * eps * (1 + c))
     g = (1 - c) / (1 + c)
-    d = dt / (2 * mu)
+    d = tr / (2 * mu)
     fe, fh = _free_mask(n, "E"), _free_mask(n, "H")
     knots = bspline.open_uniform_knots(N, p)
 
@@ -242,3 +244,74 @@ def test_material_greville_sampling_bruteforce():
                            not (c == (v + 1) / V and v + 1 < V))
                       for c in (xi[i], xi[j], xi[k])]
                 assert eps[k, j, i] == vox[vi[2], vi[1], vi[0]]
+
+
+# ------------------------------------------------- B-spline-weighted material
+def test_voxel_weights_are_bspline_mass_fractions():
+    """W[i, v] against scipy's adaptive quadrature of the oracle basis (a
+    different integration method), rows summing to one."""
+    from scipy.integrate import quad
+    from oracle import bspline
+    N, p, V = 5, 3, 7
+    W = maxwell.voxel_weights(N, p, V)
+    knots = bspline.open_uniform_knots(N, p)
+    assert np.allclose(W.sum(axis=1), 1.0, atol=1e-14)
+    for i in (0, 2, N + p - 1):
+        f = lambda x: bspline.basis(knots, p, [x])[0, i]
+        total = quad(f, 0, 1, points=list(knots[p:-p]), epsabs=1e-14, limit=200)[0]
+        # the integral of a B-spline is its knot span over p + 1
+        assert total == pytest.approx((knots[i + p + 1] - knots[i]) / (p + 1), rel=1e-12)
+        for v in range(V):
+            part = quad(f, v / V, (v + 1) / V, points=list(knots[p:-p]), epsabs=1e-14,
+                        limit=200)[0]
+            assert W[i, v] == pytest.approx(part / total, abs=1e-12)
+
+
+def test_average_material_constant_and_half_space():
+    N, p = 4, 2
+    n = N + p
+    eps = np.full((6, 5, 8), 3.5)
+    e, m, s = maxwell.average_material(N, p, eps, eps * 0 + 1.0, eps * 0)
+    assert np.allclose(e, 3.5, rtol=1e-14) and np.allclose(m, 1.0) and np.allclose(s, 0.0)
+    # a half space in x (values a | b at x = 1/2): DOF (i, j, k) takes
+    # a + (b - a) * (fraction of B_i beyond 1/2), independent of j, k
+    a, b = 2.0, 7.0
+    vox = np.where((np.arange(8) + 0.5) / 8 > 0.5, b, a)[None, None, :] * np.ones((6, 5, 8))
+    e, _, _ = maxwell.average_material(N, p, vox, np.ones_like(vox), np.zeros_like(vox))
+    from scipy.integrate import quad
+    from oracle import bspline
+    knots = bspline.open_uniform_knots(N, p)
+    for i in range(n):
+        f = lambda x: bspline.basis(knots, p, [x])[0, i]
+        frac = quad(f, 0.5, 1, points=list(knots[p:-p]))[0] / quad(f, 0, 1, points=list(knots[p:-p]))[0]
+        assert np.allclose(e[:, :, i], a + (b - a) * frac, rtol=1e-10)
+
+
+# ------------------------------------------------------- local time step
+def test_local_time_step_equals_dense_block_solve():
+    """Per-test-function tau-hat in every row coefficient (the rst
+    modification of the section on non-regular material data) against the
+    dense block systems with the same per-row tau."""
+    N, p = 3, 2
+    n = N + p
+    rng = np.random.default_rng(23)
+    eps, mu, sig = rng.uniform(1, 30, (n,) * 3), rng.uniform(0.6, 1.8, (n,) * 3), \
+        rng.uniform(0, 10, (n,) * 3)
+    tau = rng.uniform(0.02, 0.2, (n,) * 3)
+    src = DipoleSource(xs=(0.3, 0.6, 0.45), comp=2, amp=1.1, f0=1.5, t0=0.1, width=0.3)
+    dt = 0.1
+    prob = maxwell.Problem(N, p, eps, mu, sig, dt, src, local_dt=tau)
+    F = random_fields(n, seed=8)
+    E, H = prob.constrain(list(F[:3]), list(F[3:]))
+    E1, H1, t1 = prob.step(E, H, 0.05)
+    Ed, Hd = _dense_step(N, p, eps, mu, sig, dt, src, E, H, 0.05, tau=tau)
+    for a_, b_ in zip(E1 + H1, Ed + Hd):
+        np.testing.assert_allclose(a_, b_, rtol=1e-11, atol=1e-12 * max(1.0, np.abs(b_).max()))
+    assert t1 == pytest.approx(0.05 + dt)
+    # tau-hat = dt everywhere is the plain step
+    plain = maxwell.Problem(N, p, eps, mu, sig, dt, src)
+    loc = maxwell.Problem(N, p, eps, mu, sig, dt, src, local_dt=np.full((n,) * 3, dt))
+    a1, b1, _ = plain.step(E, H, 0.05)
+    a2, b2, _ = loc.step(E, H, 0.05)
+    for x, y in zip(a1 + b1, a2 + b2):
+        assert np.array_equal(x, y)
