@@ -168,6 +168,21 @@ const char* adi_last_error(const adi_ctx* ctx);
 void adi_destroy(adi_ctx* ctx);
 
 /*
+ * Manufactured solution of section "Numerical code verification with
+ * manufactured solution" (unit cube, eps = mu = 1, sigma = 0, PEC):
+ * u_A = g u^1_11 + 2 g u^2_11 + 3 g u^3_11, g = 2/sqrt(14), with the magnetic
+ * part of u^2 of the sign that solves Maxwell's equations.  The integrals use
+ * q Gauss points per element and axis (1 <= q <= 16).
+ * adi_mms_project: the state becomes the L2 projection of u_A(t) onto the
+ *   PEC-constrained spline space (mass solves), and the time t.
+ * adi_mms_errors: at the context's time (waits for the stream),
+ *   out[0] = ||E_h - E||_L2, out[1] = the H(curl) norm of E_h - E,
+ *   out[2], out[3] the same for H (absolute).
+ */
+int adi_mms_project(adi_ctx* ctx, int q, double t);
+int adi_mms_errors(adi_ctx* ctx, int q, double* out);
+
+/*
  * Single hot-path stages on host buffers (float64 in and out), for testing
  * one step of the method against a reference.  Each runs the same kernels as
  * adi_step and synchronises.

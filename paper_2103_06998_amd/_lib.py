@@ -44,6 +44,8 @@ SIGNATURES = {
     "adi_destroy": (None, [_P]),
     "adi_rhs": (_I, [_P, _I, _I, _D, ctypes.c_double, _D]),
     "adi_solve": (_I, [_P, _I, _I, _D]),
+    "adi_mms_project": (_I, [_P, _I, ctypes.c_double]),
+    "adi_mms_errors": (_I, [_P, _I, _D]),
     "adi_profile_run": (_I, [_P, _I]),
     "adi_profile_read": (_I, [_P, _I, ctypes.POINTER(_I), ctypes.POINTER(_I),
                               ctypes.POINTER(_I), ctypes.POINTER(_I),

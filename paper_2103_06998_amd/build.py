@@ -21,7 +21,8 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           # packed FP32 instructions are disabled for all device code
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-I", os.path.join(ROOT, "include"), "-I", CSRC]
-SOURCES = ["kernels.hip", "adimx.cpp", "host_basis.cpp", "closure.hip", "closure.cpp"]
+SOURCES = ["kernels.hip", "adimx.cpp", "host_basis.cpp", "closure.hip", "closure.cpp",
+           "mms.hip"]
 
 
 def _compile(src: str) -> str:

@@ -13,6 +13,7 @@
 #include "adimx.h"
 #include "adimx_internal.h"
 #include "closure_internal.h"
+#include "mms_internal.h"
 
 #include <algorithm>
 #include <cmath>
@@ -101,6 +102,12 @@ struct adi_ctx {
   int* cl_flag = nullptr;       // [0] gate flag, [1] rejected-correction counter
   bool cl_mat_valid = false;    // cl_mat matches the last factorisation
   bool cl_marked = false;       // cl_prev holds a state
+
+  // manufactured-solution tools (allocated on first use)
+  int mms_q = 0;
+  double* mms_tab = nullptr;    // x, w, bv, bd of the q-point rule (one axis)
+  double* mms_vals = nullptr;   // solution at the Gauss points, 6 Q^3
+  double* mms_part = nullptr;   // error partial sums, 4 per block
 
   bool refine() const { return prec == ADI_FP32_REFINE; }
 };
@@ -984,6 +991,9 @@ void adi_destroy(adi_ctx* c) {
   if (c->cl_mat) hipFree(c->cl_mat);
   if (c->cl_red) hipFree(c->cl_red);
   if (c->cl_flag) hipFree(c->cl_flag);
+  if (c->mms_tab) hipFree(c->mms_tab);
+  if (c->mms_vals) hipFree(c->mms_vals);
+  if (c->mms_part) hipFree(c->mms_part);
   if (c->cap) hipStreamDestroy(c->cap);
   if (c->side) hipStreamDestroy(c->side);
   for (hipEvent_t e : c->fork_ev) hipEventDestroy(e);
@@ -1227,6 +1237,146 @@ int adi_closure_rejected(adi_ctx* c, int* count) {
   if (!c->cl_flag) return ADI_OK;
   HIPCHK(c, hipStreamSynchronize(c->stream));
   HIPCHK(c, hipMemcpy(count, c->cl_flag + 1, sizeof(int), hipMemcpyDeviceToHost));
+  return ADI_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------ manufactured solution
+namespace {
+
+// Gauss tables of the q-point rule on every element (one axis; the patch
+// is a cube) on the device, and the buffers of the projection and errors.
+int mms_ready(adi_ctx* c, int q) {
+  if (q < 1 || q > 16) return fail(c, ADI_EINVAL, "quadrature points per element must be 1..16");
+  if (c->mms_q == q) return ADI_OK;
+  const int N = c->N, p = c->p, Q = N * q;
+  std::vector<double> gx, gw;
+  gauss_legendre(q, gx, gw);
+  const std::vector<double> t = open_knots(N, p);
+  std::vector<double> tab(size_t(Q) * (2 + 2 * (p + 1)));
+  double* X = tab.data();
+  double* Wt = X + Q;
+  double* BV = Wt + Q;
+  double* BD = BV + size_t(Q) * (p + 1);
+  std::vector<double> v(p + 1), d(p + 1);
+  for (int e = 0; e < N; ++e)
+    for (int g = 0; g < q; ++g) {
+      const int a = e * q + g;
+      X[a] = (e + 0.5 * (gx[g] + 1.0)) / N;
+      Wt[a] = 0.5 * gw[g] / N;
+      basis_on_span(t, p, e + p, X[a], v.data(), d.data());
+      for (int r = 0; r <= p; ++r) {
+        BV[size_t(a) * (p + 1) + r] = v[r];
+        BD[size_t(a) * (p + 1) + r] = d[r];
+      }
+    }
+  if (c->mms_tab) hipFree(c->mms_tab);
+  if (c->mms_vals) hipFree(c->mms_vals);
+  c->mms_tab = nullptr;
+  c->mms_vals = nullptr;
+  c->mms_q = 0;
+  HIPCHK(c, hipMalloc(reinterpret_cast<void**>(&c->mms_tab), tab.size() * 8));
+  HIPCHK(c, hipMemcpy(c->mms_tab, tab.data(), tab.size() * 8, hipMemcpyHostToDevice));
+  HIPCHK(c, hipMalloc(reinterpret_cast<void**>(&c->mms_vals), 6 * size_t(Q) * Q * Q * 8));
+  if (!c->mms_part) HIPCHK(c, hipMalloc(reinterpret_cast<void**>(&c->mms_part), 2048 * 4 * 8));
+  c->mms_q = q;
+  return ADI_OK;
+}
+
+mms::Tables mms_tables(const adi_ctx* c) {
+  const int Q = c->N * c->mms_q, p = c->p;
+  mms::Tables tb{};
+  tb.x = c->mms_tab;
+  tb.w = c->mms_tab + Q;
+  tb.bv = c->mms_tab + 2 * Q;
+  tb.bd = c->mms_tab + 2 * Q + size_t(Q) * (p + 1);
+  tb.N = c->N;
+  tb.p = p;
+  tb.q = c->mms_q;
+  return tb;
+}
+
+// (M (x) M (x) M)^-1 on the three components of buf (E or H boundary rows).
+template <typename T>
+hipError_t enqueue_mass_solves(adi_ctx* c, int kindH, void* buf, hipStream_t s) {
+  for (int ax = 0; ax < 3; ++ax) {
+    SweepArgs w{};
+    for (int ci = 0; ci < 3; ++ci) {
+      void* io = comp(buf, ci, c);
+      const int v = dirichlet(kindH, ci, ax) ? 1 : 0;
+      SweepDesc& d = w.d[ci];
+      d.axis = ax;
+      d.in = io;
+      d.out = io;
+      d.L = c->shL[v];
+      d.U = c->shU[v];
+      d.D = c->shD[v];
+      d.spk = c->spike_ok ? c->spk[v] : nullptr;
+      d.modified = 0;
+    }
+    w.n = c->n;
+    w.nlines = c->n * c->n;
+    w.xaxis = ax == 0;
+    w.spike = c->spike_ok ? 1 : 0;
+    hipError_t e = launch_sweep<T>(c->p, 3, w, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+int adi_mms_project(adi_ctx* c, int q, double t) {
+  if (!c || !std::isfinite(t)) return ADI_EINVAL;
+  if (!c->factored) return fail(c, ADI_ESTATE, "adi_factor first");
+  int st = mms_ready(c, q);
+  if (st != ADI_OK) return st;
+  const mms::Tables tb = mms_tables(c);
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, mms::launch_exact(tb, t, c->mms_vals, c->cap));
+  hipError_t e;
+  if (c->esz == 8) {
+    e = mms::launch_project_rhs<double>(tb, c->mms_vals, static_cast<double*>(c->B[0]), c->cap);
+    if (e == hipSuccess) e = enqueue_mass_solves<double>(c, 0, c->B[0], c->cap);
+    if (e == hipSuccess) e = enqueue_mass_solves<double>(c, 1, c->B[1], c->cap);
+  } else {
+    e = mms::launch_project_rhs<float>(tb, c->mms_vals, static_cast<float*>(c->B[0]), c->cap);
+    if (e == hipSuccess) e = enqueue_mass_solves<float>(c, 0, c->B[0], c->cap);
+    if (e == hipSuccess) e = enqueue_mass_solves<float>(c, 1, c->B[1], c->cap);
+  }
+  HIPCHK(c, e);
+  HIPCHK(c, hipMemcpyAsync(c->d_t, &t, 8, hipMemcpyHostToDevice, c->cap));
+  HIPCHK(c, hipStreamSynchronize(c->cap));
+  c->t = t;
+  return ADI_OK;
+}
+
+int adi_mms_errors(adi_ctx* c, int q, double* out) {
+  if (!c || !out) return ADI_EINVAL;
+  if (!c->ws) return fail(c, ADI_ESTATE, "no state");
+  int st = mms_ready(c, q);
+  if (st != ADI_OK) return st;
+  const mms::Tables tb = mms_tables(c);
+  int nblk = 0;
+  HIPCHK(c, c->esz == 8
+                ? mms::launch_errors<double>(tb, static_cast<const double*>(c->B[0]), c->t,
+                                             c->mms_part, &nblk, c->stream)
+                : mms::launch_errors<float>(tb, static_cast<const float*>(c->B[0]), c->t,
+                                            c->mms_part, &nblk, c->stream));
+  std::vector<double> part(size_t(nblk) * 4);
+  HIPCHK(c, hipMemcpyAsync(part.data(), c->mms_part, part.size() * 8, hipMemcpyDeviceToHost,
+                           c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  double sum[4] = {0, 0, 0, 0};
+  for (int b = 0; b < nblk; ++b)
+    for (int k = 0; k < 4; ++k) sum[k] += part[size_t(b) * 4 + k];
+  out[0] = std::sqrt(sum[0]);
+  out[1] = std::sqrt(sum[0] + sum[1]);
+  out[2] = std::sqrt(sum[2]);
+  out[3] = std::sqrt(sum[2] + sum[3]);
   return ADI_OK;
 }
 

@@ -1,0 +1,197 @@
+// Manufactured solution of the paper's verification section (unit cube,
+// eps = mu = 1, PEC): u_A = g u^1_11 + 2 g u^2_11 + 3 g u^3_11 with
+// g = 2 / sqrt(14), omega = pi sqrt(2), the magnetic part of u^2 taken with
+// the sign that makes it a Maxwell solution (the printed one is not).  Its
+// curls follow from Maxwell's equations: curl E = -dH/dt, curl H = dE/dt.
+// Kernels: the solution at Gauss points, L2-projection right-hand sides, and
+// L2 / H(curl) error sums of a spline state.
+#include "mms_internal.h"
+
+#include <cmath>
+
+namespace adimx {
+namespace mms {
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+// E, H and (with curls) curl E, curl H of u_A at (x, y, z, t).
+__device__ void exact(double x, double y, double z, double t, double* e, double* h,
+                      double* ce, double* ch) {
+  const double g = 2.0 / sqrt(14.0), s2 = sqrt(2.0), w = kPi * s2;
+  const double sx = sin(kPi * x), cx = cos(kPi * x), sy = sin(kPi * y), cy = cos(kPi * y),
+               sz = sin(kPi * z), cz = cos(kPi * z);
+  const double C = cos(w * t), S = sin(w * t), dC = -w * sin(w * t), dS = w * cos(w * t);
+  // spatial parts
+  const double e1 = g * sy * sz, e2 = 2.0 * g * sx * sz, e3 = 3.0 * g * sx * sy;
+  const double h1 = g / s2 * (2.0 * sx * cz - 3.0 * sx * cy);
+  const double h2 = g / s2 * (-sy * cz + 3.0 * cx * sy);
+  const double h3 = g / s2 * (cy * sz - 2.0 * cx * sz);
+  e[0] = e1 * C; e[1] = e2 * C; e[2] = e3 * C;
+  h[0] = h1 * S; h[1] = h2 * S; h[2] = h3 * S;
+  if (ce) {
+    ce[0] = -h1 * dS; ce[1] = -h2 * dS; ce[2] = -h3 * dS;
+    ch[0] = e1 * dC; ch[1] = e2 * dC; ch[2] = e3 * dC;
+  }
+}
+
+__global__ void exact_kernel(Tables tb, double t, double* vals) {
+  const int Q = tb.N * tb.q;
+  const size_t Q3 = size_t(Q) * Q * Q;
+  for (size_t idx = size_t(blockIdx.x) * blockDim.x + threadIdx.x; idx < Q3;
+       idx += size_t(gridDim.x) * blockDim.x) {
+    const int a = int(idx % Q), b = int((idx / Q) % Q), c = int(idx / (size_t(Q) * Q));
+    double e[3], h[3];
+    exact(tb.x[a], tb.x[b], tb.x[c], t, e, h, nullptr, nullptr);
+    for (int k = 0; k < 3; ++k) {
+      vals[k * Q3 + idx] = e[k];
+      vals[(3 + k) * Q3 + idx] = h[k];
+    }
+  }
+}
+
+// One thread per coefficient (i, j, k) and component: sum over the elements
+// of its support and their Gauss points.
+template <typename T>
+__global__ void project_rhs_kernel(Tables tb, const double* __restrict__ vals, T* __restrict__ st) {
+  const int N = tb.N, p = tb.p, q = tb.q, n = N + p, Q = N * q;
+  const size_t Q3 = size_t(Q) * Q * Q, D = size_t(n) * n * n;
+  for (size_t idx = size_t(blockIdx.x) * blockDim.x + threadIdx.x; idx < 6 * D;
+       idx += size_t(gridDim.x) * blockDim.x) {
+    const int comp = int(idx / D);
+    const size_t o = idx % D;
+    const int i = int(o % n), j = int((o / n) % n), k = int(o / (size_t(n) * n));
+    const bool bi = i == 0 || i == n - 1, bj = j == 0 || j == n - 1, bk = k == 0 || k == n - 1;
+    const int cc = comp % 3;
+    const bool bnd = comp < 3 ? ((cc != 0 && bi) || (cc != 1 && bj) || (cc != 2 && bk))
+                              : ((cc == 0 && bi) || (cc == 1 && bj) || (cc == 2 && bk));
+    double s = 0.0;
+    if (!bnd) {
+      for (int ez = max(k - p, 0); ez <= min(k, N - 1); ++ez)
+        for (int ey = max(j - p, 0); ey <= min(j, N - 1); ++ey)
+          for (int ex = max(i - p, 0); ex <= min(i, N - 1); ++ex)
+            for (int gz = 0; gz < q; ++gz) {
+              const int c = ez * q + gz;
+              const double wz = tb.w[c] * tb.bv[c * (p + 1) + (k - ez)];
+              for (int gy = 0; gy < q; ++gy) {
+                const int b = ey * q + gy;
+                const double wy = wz * tb.w[b] * tb.bv[b * (p + 1) + (j - ey)];
+                for (int gx = 0; gx < q; ++gx) {
+                  const int a = ex * q + gx;
+                  s += wy * tb.w[a] * tb.bv[a * (p + 1) + (i - ex)] *
+                       vals[comp * Q3 + (size_t(c) * Q + b) * Q + a];
+                }
+              }
+            }
+    }
+    st[idx] = T(s);
+  }
+}
+
+// One thread per quadrature point: spline values and first derivatives of
+// the six components, squared errors against u_A weighted by the Gauss
+// weights, block sums in float64.
+template <typename T>
+__global__ __launch_bounds__(256) void errors_kernel(Tables tb, const T* __restrict__ st, double t,
+                                                     double* __restrict__ partial) {
+  const int N = tb.N, p = tb.p, q = tb.q, n = N + p, Q = N * q;
+  const size_t Q3 = size_t(Q) * Q * Q, D = size_t(n) * n * n;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (size_t idx = size_t(blockIdx.x) * blockDim.x + threadIdx.x; idx < Q3;
+       idx += size_t(gridDim.x) * blockDim.x) {
+    const int a = int(idx % Q), b = int((idx / Q) % Q), c = int(idx / (size_t(Q) * Q));
+    const int fx = a / q, fy = b / q, fz = c / q;
+    const double* vx = tb.bv + a * (p + 1);
+    const double* vy = tb.bv + b * (p + 1);
+    const double* vz = tb.bv + c * (p + 1);
+    const double* dx = tb.bd + a * (p + 1);
+    const double* dy = tb.bd + b * (p + 1);
+    const double* dz = tb.bd + c * (p + 1);
+    // f[comp][0] value, [1] d/dx, [2] d/dy, [3] d/dz
+    double f[6][4];
+    for (int comp = 0; comp < 6; ++comp) {
+      const T* cf = st + comp * D;
+      double v0 = 0, v1 = 0, v2 = 0, v3 = 0;
+      for (int r = 0; r <= p; ++r)
+        for (int sidx = 0; sidx <= p; ++sidx) {
+          const T* row = cf + (size_t(fz + r) * n + (fy + sidx)) * n + fx;
+          double rv = 0.0, rd = 0.0;
+          for (int u = 0; u <= p; ++u) {
+            const double cval = double(row[u]);
+            rv += cval * vx[u];
+            rd += cval * dx[u];
+          }
+          v0 += vz[r] * vy[sidx] * rv;
+          v1 += vz[r] * vy[sidx] * rd;
+          v2 += vz[r] * dy[sidx] * rv;
+          v3 += dz[r] * vy[sidx] * rv;
+        }
+      f[comp][0] = v0; f[comp][1] = v1; f[comp][2] = v2; f[comp][3] = v3;
+    }
+    double e[3], h[3], ce[3], ch[3];
+    exact(tb.x[a], tb.x[b], tb.x[c], t, e, h, ce, ch);
+    const double wq = tb.w[a] * tb.w[b] * tb.w[c];
+    for (int fld = 0; fld < 2; ++fld) {
+      const double (*F)[4] = f + 3 * fld;
+      const double* ex = fld ? h : e;
+      const double* cx = fld ? ch : ce;
+      // curl: (d2 F3 - d3 F2, d3 F1 - d1 F3, d1 F2 - d2 F1)
+      const double cu[3] = {F[2][2] - F[1][3], F[0][3] - F[2][1], F[1][1] - F[0][2]};
+      double l2 = 0.0, cs = 0.0;
+      for (int k = 0; k < 3; ++k) {
+        const double d = F[k][0] - ex[k], dc = cu[k] - cx[k];
+        l2 += d * d;
+        cs += dc * dc;
+      }
+      acc[2 * fld] += wq * l2;
+      acc[2 * fld + 1] += wq * cs;
+    }
+  }
+  __shared__ double red[4][256];
+  for (int k = 0; k < 4; ++k) red[k][threadIdx.x] = acc[k];
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w)
+      for (int k = 0; k < 4; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) partial[blockIdx.x * 4 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+int grid_for(size_t work) { return int(std::min<size_t>((work + 255) / 256, 2048)); }
+
+}  // namespace
+
+hipError_t launch_exact(const Tables& tb, double t, double* vals, hipStream_t s) {
+  const size_t Q = size_t(tb.N) * tb.q;
+  hipLaunchKernelGGL(exact_kernel, dim3(grid_for(Q * Q * Q)), dim3(256), 0, s, tb, t, vals);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_project_rhs(const Tables& tb, const double* vals, T* state, hipStream_t s) {
+  const size_t n = size_t(tb.N) + tb.p;
+  hipLaunchKernelGGL(project_rhs_kernel<T>, dim3(grid_for(6 * n * n * n)), dim3(256), 0, s, tb,
+                     vals, state);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_errors(const Tables& tb, const T* state, double t, double* partial, int* nblk,
+                         hipStream_t s) {
+  const size_t Q = size_t(tb.N) * tb.q;
+  const int g = grid_for(Q * Q * Q);
+  *nblk = g;
+  hipLaunchKernelGGL(errors_kernel<T>, dim3(g), dim3(256), 0, s, tb, state, t, partial);
+  return hipGetLastError();
+}
+
+template hipError_t launch_project_rhs<double>(const Tables&, const double*, double*, hipStream_t);
+template hipError_t launch_project_rhs<float>(const Tables&, const double*, float*, hipStream_t);
+template hipError_t launch_errors<double>(const Tables&, const double*, double, double*, int*,
+                                          hipStream_t);
+template hipError_t launch_errors<float>(const Tables&, const float*, double, double*, int*,
+                                         hipStream_t);
+
+}  // namespace mms
+}  // namespace adimx

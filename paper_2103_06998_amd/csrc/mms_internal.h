@@ -1,0 +1,35 @@
+// Internal declarations of the manufactured-solution kernels (not ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace adimx {
+namespace mms {
+
+// Quadrature tables of one axis: Q = N q Gauss points, for point a the
+// basis functions a/q .. a/q + p (element a/q) with values bv[a*(p+1) + r]
+// and derivatives bd[a*(p+1) + r]; coordinates x[a] and weights w[a].
+struct Tables {
+  const double* x;
+  const double* w;
+  const double* bv;
+  const double* bd;
+  int N, p, q;
+};
+
+// vals[c * Q^3 + point] = component c (E1..E3, H1..H3) of the manufactured
+// solution at time t on the tensor grid of quadrature points (x fastest).
+hipError_t launch_exact(const Tables& tb, double t, double* vals, hipStream_t s);
+// L2 projection right-hand sides (f_c, B_i B_j B_k) into the six state
+// components (type T, n^3 each), constrained coefficients set to zero.
+template <typename T>
+hipError_t launch_project_rhs(const Tables& tb, const double* vals, T* state, hipStream_t s);
+// Per-block partial sums of the squared errors of the state against the
+// manufactured solution at time t: [block][0] E L2, [1] E curl, [2] H L2,
+// [3] H curl.  Returns the number of blocks written (nblk <= max_blocks).
+template <typename T>
+hipError_t launch_errors(const Tables& tb, const T* state, double t, double* partial,
+                         int* nblk, hipStream_t s);
+
+}  // namespace mms
+}  // namespace adimx

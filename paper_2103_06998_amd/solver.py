@@ -191,3 +191,15 @@ class Solver:
         c = ctypes.c_int()
         self._check(self.lib.adi_closure_rejected(self.h, ctypes.byref(c)))
         return c.value
+
+    # -- manufactured solution ------------------------------------------------
+    def mms_project(self, q: int = 0, t: float = 0.0):
+        """State = L2 projection of the manufactured solution at time t."""
+        self._check(self.lib.adi_mms_project(self.h, int(q or self.p + 3), float(t)))
+
+    def mms_errors(self, q: int = 0) -> dict:
+        """Absolute L2 and H(curl) errors of E and H against the manufactured
+        solution at the current time."""
+        out = np.empty(4)
+        self._check(self.lib.adi_mms_errors(self.h, int(q or self.p + 3), _lib.dptr(out)))
+        return {"E_L2": out[0], "E_Hcurl": out[1], "H_L2": out[2], "H_Hcurl": out[3]}
