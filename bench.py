@@ -172,6 +172,8 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-256", action="store_true",
+                    help="skip the 256^3 p=2 throughput lines (reported beside the headline)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path has no "
@@ -187,6 +189,18 @@ def main():
     log(f"fp32_refine: {res32['ms_per_step']:.3f} ms/step {res32['value']:.3e} DOF/s")
     res64 = run_gpu("fp64", w, args.steps, args.warmup)
     log(f"fp64: {res64['ms_per_step']:.3f} ms/step {res64['value']:.3e} DOF/s")
+    big = None
+    if not args.no_256:
+        w4 = workloads.make("shell256")
+        n4 = w4.N + w4.p
+        big = {"workload": "shell256: 256^3 elements, p=2, n=258, 256^3 shell map (seed 4), "
+                           "dipole in air, dt=1/512, 50 steps", "dofs": 6 * n4 ** 3}
+        for prec in ("fp32_refine", "fp64"):
+            r = run_gpu(prec, w4, w4.steps, args.warmup)
+            log(f"shell256 {prec}: {r['ms_per_step']:.3f} ms/step {r['value']:.3e} DOF/s")
+            big[prec] = {"value": r["value"], "ms_per_step": r["ms_per_step"],
+                         "roofline": r["roofline"], "step_frac_hbm": r["step_frac_hbm"],
+                         "finite": r["finite"]}
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w)
@@ -219,6 +233,7 @@ def main():
                                "step_frac_hbm": res32["step_frac_hbm"],
                                "step_algorithmic_bytes": res32["step_algorithmic_bytes"],
                                "finite": res32["finite"]},
+        "shell256": big,
     }
     print(json.dumps(out), flush=True)
 

@@ -448,10 +448,23 @@ hipError_t enqueue_step_t(adi_ctx* c, hipStream_t s) {
                           comp(Ein, 0, c),  comp(Ein, 1, c),  comp(Ein, 2, c),
                           comp(Eout, 0, c), comp(Eout, 1, c), comp(Eout, 2, c)};
       void* out[3] = {comp(Hout, 0, c), comp(Hout, 1, c), comp(Hout, 2, c)};
-      RhsArgs<T> a = rhs_args<T>(c, f, 9, out, 1, sub);
-      hipError_t e = timed(c, s, kKindRhsH, 3, 0, [&] {
-        return launch_rhs<T>(sub == 1 ? kStageH1 : kStageH2, c->p, a, s);
-      });
+      hipError_t e;
+      if (!c->refine()) {
+        RhsArgs<T> a = rhs_args<T>(c, f, 9, out, 1, sub);
+        e = timed(c, s, kKindRhsH, 3, 0, [&] {
+          return launch_rhs<T>(sub == 1 ? kStageH1 : kStageH2, c->p, a, s);
+        });
+      } else {
+        // float64 arithmetic on the float32 fields keeps the H right-hand
+        // side's cancellations out of float32 (H has no correction solve)
+        RhsArgs<double> a = rhs_args<double>(c, f, 9, out, 1, sub);
+        a.coef[0] = c->coef64[3];
+        a.band = c->band64;
+        a.zw = c->zw64;
+        e = timed(c, s, kKindRhsH, 3, 0, [&] {
+          return launch_rhs_e64(sub == 1 ? kStageH1 : kStageH2, c->p, a, s);
+        });
+      }
       if (e != hipSuccess) return e;
       // H: x, y, z (all shared factors); the last launch advances the time
       for (int ax = 0; ax < 3; ++ax) {

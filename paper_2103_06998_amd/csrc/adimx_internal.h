@@ -126,8 +126,9 @@ struct FactorArgs {
 template <typename T>
 hipError_t launch_rhs(int stage, int p, const RhsArgs<T>& a, hipStream_t stream);
 hipError_t launch_residual(int stage, int p, const RhsArgs<double>& a, hipStream_t stream);
-// E right-hand sides in float64 arithmetic from float32 fields: float64
-// outputs (out) and their float32 copies (out2).
+// Right-hand sides in float64 arithmetic from float32 fields: E stages with
+// float64 outputs (out) and their float32 copies (out2), H stages with
+// float32 outputs.
 hipError_t launch_rhs_e64(int stage, int p, const RhsArgs<double>& a, hipStream_t stream);
 template <typename T>
 hipError_t launch_sweep(int p, int ndesc, const SweepArgs& a, hipStream_t stream);

@@ -1054,6 +1054,8 @@ hipError_t launch_e64_p(int stage, const RhsArgs<double>& a, hipStream_t s) {
   switch (stage) {
     case kStageE1: return launch_rhs_t<float, double, double, P, kStageE1>(a, s);
     case kStageE2: return launch_rhs_t<float, double, double, P, kStageE2>(a, s);
+    case kStageH1: return launch_rhs_t<float, double, float, P, kStageH1>(a, s);
+    case kStageH2: return launch_rhs_t<float, double, float, P, kStageH2>(a, s);
   }
   return hipErrorInvalidValue;
 }
