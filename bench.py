@@ -156,13 +156,17 @@ def cpu_baseline(w):
     E, H = prob.constrain(E, H)
     r0 = resource.getrusage(resource.RUSAGE_SELF)
     t0 = time.perf_counter()
-    prob.step(E, H, 0.45)
+    steps, t = 0, 0.45
+    # whole steps until about 10 s of work (at most 8 steps)
+    while steps < 8 and (steps == 0 or time.perf_counter() - t0 < 10.0):
+        E, H, t = prob.step(E, H, t)
+        steps += 1
     wall = time.perf_counter() - t0
     r1 = resource.getrusage(resource.RUSAGE_SELF)
     cpu = (r1.ru_utime - r0.ru_utime) + (r1.ru_stime - r0.ru_stime)
-    return {"value": 6.0 * n ** 3 / wall, "unit": "field DOF-updates/s",
+    return {"value": 6.0 * n ** 3 * steps / wall, "unit": "field DOF-updates/s",
             "cores": max(1, int(round(cpu / wall))), "kind": "oracle",
-            "sample": f"1 full step (both substeps) of the {w.N}^3 p={w.p} workload, "
+            "sample": f"{steps} full step(s) (both substeps) of the {w.N}^3 p={w.p} workload, "
                       f"float64 NumPy oracle, {wall:.1f} s wall, {cpu:.1f} s CPU"}
 
 
