@@ -57,8 +57,6 @@ enum RhsStage : int {
   kStageE2 = 1,   // E right-hand sides, substep 2 (eq. discrete3)
   kStageH1 = 2,   // H right-hand sides, substep 1 (eq. discrete2)
   kStageH2 = 3,   // H right-hand sides, substep 2 (eq. discrete4)
-  kStageR1 = 4,   // E residual b - P x of substep 1 (float64 correction)
-  kStageR2 = 5,   // E residual of substep 2
   kStageQ1 = 6,   // E residual b - P x of substep 1 from a given float64 b
   kStageQ2 = 7,   // the same for substep 2
 };

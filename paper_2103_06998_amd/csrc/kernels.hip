@@ -30,8 +30,6 @@ constexpr int OM = 0, OA = 1, OB = 2, OS = 3;
 //  H stages (fields H1..3, E_old1..3, E_new1..3; groups 1, delta):
 //    discrete2: RH1 = MMM H1 - d MAM E3 + d MMA E2', ...
 //    discrete4: RH1 = MMM H1 + d MMA E2' - d MAM E3'', ... (sign of scheme1d)
-//  Residual stages (fields E, H, X = float32 solution; groups gamma, beta,
-//    alpha, 1): the E right-hand side minus (M..M) X minus alpha (..S..) X.
 //  Q stages (fields X; groups alpha, 1): a given float64 right-hand side b
 //    minus (M..M) X minus alpha (..S..) X.
 template <int STAGE>
@@ -40,8 +38,6 @@ template <> struct StageInfo<kStageE1> { static constexpr int NT = 12, NF = 6, N
 template <> struct StageInfo<kStageE2> { static constexpr int NT = 12, NF = 6, NG = 3; };
 template <> struct StageInfo<kStageH1> { static constexpr int NT = 9, NF = 9, NG = 2; };
 template <> struct StageInfo<kStageH2> { static constexpr int NT = 9, NF = 9, NG = 2; };
-template <> struct StageInfo<kStageR1> { static constexpr int NT = 18, NF = 9, NG = 4; };
-template <> struct StageInfo<kStageR2> { static constexpr int NT = 18, NF = 9, NG = 4; };
 template <> struct StageInfo<kStageQ1> { static constexpr int NT = 6, NF = 3, NG = 4; };
 template <> struct StageInfo<kStageQ2> { static constexpr int NT = 6, NF = 3, NG = 4; };
 
@@ -80,9 +76,7 @@ __host__ __device__ constexpr Term get_term(int i) {
     return t;
   }
   if (i < 9) return curl_and_mass[i];
-  const bool sub2 = (STAGE == kStageE2 || STAGE == kStageR2);
-  if (i < 12) return sub2 ? r_sub2[i - 9] : r_sub1[i - 9];
-  return sub2 ? px_sub2[i - 12] : px_sub1[i - 12];
+  return STAGE == kStageE2 ? r_sub2[i - 9] : r_sub1[i - 9];
 }
 
 // Per output component: the input fields it reads (local slots) and its
@@ -139,14 +133,13 @@ __device__ __forceinline__ void static_for(F&& f) {
 constexpr int kTX = 32, kTY = 8, kCols = kTX * kTY;
 constexpr int kXcds = 8;  // MI355X: 8 accelerator complex dies, one L2 each
 constexpr int kRhsThreads = kCols;  // one block per (tile, output component)
-constexpr int kPrefetch = 2;        // input planes loaded ahead of use
 
-// The residual stages keep four accumulator groups per thread; their x band
-// rows are read from LDS instead of registers to stay clear of spills.
+// The Q stages keep four accumulator groups per thread; their x band rows
+// are read from LDS instead of registers to stay clear of spills.
 template <int STAGE>
 constexpr bool xband_in_lds() { return StageInfo<STAGE>::NG == 4; }
 
-// LDS of one RHS block: y-pass results (two buffers), x band rows (residual
+// LDS of one RHS block: y-pass results (two buffers), x band rows (Q
 // stages), the y band rows of the tile and the z weights of the chunk's
 // input planes.
 template <typename TC, int P, int STAGE>
@@ -165,7 +158,7 @@ size_t rhs_lds_bytes(int zchunk) {
 // planes are marched along z.  The y operators are applied by one wave per
 // (field, operator) pair of the component: lane = x column of the tile with
 // its p-halo, holding the 2p + kTY values of its column (loaded straight
-// from global memory kPrefetch planes ahead) and producing kTY values into
+// from global memory two planes ahead) and producing kTY values into
 // LDS (double buffered, so one barrier per plane suffices).  The x operators
 // are then applied per output column with the thread's band rows in
 // registers, and each result is scattered into a register queue of 2p+1
@@ -182,15 +175,15 @@ __global__ __launch_bounds__(kRhsThreads) void rhs_kernel(RhsArgs<TC> a,
   constexpr bool kE = !(STAGE == kStageH1 || STAGE == kStageH2);
   constexpr bool kQ = STAGE == kStageQ1 || STAGE == kStageQ2;
   constexpr int NWAVES = kRhsThreads / 64;
-  constexpr int NPW = (CT.maxnp + NWAVES - 1) / NWAVES;  // pairs per wave
-  constexpr int NPF = NPW > 1 ? 1 : kPrefetch;           // planes in flight per pair
-  constexpr int GSZ = CT.maxnp * kTY * HX;                // one y-pass buffer
+  static_assert(CT.maxnp <= NWAVES, "one (field, y operator) pair per wave");
   static_assert(HX <= 64, "one lane per x column in the y pass");
+  constexpr int GSZ = CT.maxnp * kTY * HX;  // one y-pass buffer
+  constexpr int NCF = kE ? 3 : 1;           // per-row coefficients of an output
 
   extern __shared__ __align__(16) unsigned char smem[];
   TC* sG = reinterpret_cast<TC*>(smem);  // [2][pair][yy][x]
   constexpr bool kXL = xband_in_lds<STAGE>();
-  TC* sBX = sG + 2 * GSZ;                   // x band rows (residual stages only)
+  TC* sBX = sG + 2 * GSZ;                   // x band rows (Q stages only)
   TC* sYB = sBX + (kXL ? 4 * kTX * W : 0);  // y band rows [op][yy][d] of the tile
   TC* sZW = sYB + 4 * kTY * W;              // z weights [plane - kbeg][op][q]
 
@@ -223,10 +216,9 @@ __global__ __launch_bounds__(kRhsThreads) void rhs_kernel(RhsArgs<TC> a,
   const int t0 = bz * a.zchunk;
   const int t1 = min(n, t0 + a.zchunk);
   const int i = i0 + tx, j = j0 + ty;
-  const int npc = CT.np[comp];
 
   // x band rows of this thread's output column (registers, or LDS for the
-  // residual stages)
+  // Q stages)
   TC xb[kXL ? 1 : 4][W];
   if (kXL) {
     for (int idx = tid; idx < 4 * kTX * W; idx += kRhsThreads) {
@@ -252,30 +244,40 @@ __global__ __launch_bounds__(kRhsThreads) void rhs_kernel(RhsArgs<TC> a,
     sZW[idx] = zw[(size_t(op) * n + kbeg + kk) * W + q];
   }
 
-  // This wave's (field, y operator) pairs and this lane's column: x = i0 - P
-  // + lane, rows y = j0 - P + m (m < HY); values outside the patch are zero.
-  const int gi = i0 - P + lane;
-  const bool colok = lane < HX && gi >= 0 && gi < n;
-  const TI* psrc[NPW];
-  int pyop[NPW], pid[NPW];
+  // This wave's (field, y operator) pair and this lane's column x = i0 - P +
+  // lane, rows y = j0 - P + m (m < HY).  Every global load in the plane loop
+  // is issued unconditionally: columns and rows outside the grid are clamped
+  // to its edge (their band weights are zero, so the values read there never
+  // contribute), a wave without a pair reads a single address, and planes
+  // past the chunk re-read its last one.  With no load skipped by a branch
+  // the compiler counts the loads in flight exactly, and each wait for a
+  // plane or a coefficient leaves the younger prefetches in flight.
+  const int npc = CT.np[comp];
+  const bool on = wave < npc;
+  const int pr = on ? wave : 0;
+  const int pyop = CT.pyop[comp][pr];
+  // Addresses are a block-uniform row or plane pointer plus a 32-bit lane
+  // offset (n^2 < 2^31), which keeps one offset register per lane.
+  const TI* fsrc = static_cast<const TI*>(a.f[CT.field[comp][CT.pslot[comp][pr]]]);
+  const unsigned loff = on ? unsigned(min(max(i0 - P + lane, 0), n - 1)) : 0u;
+  const size_t pstride = on ? plane : 0;
+  int rows[HY];
 #pragma unroll
-  for (int q = 0; q < NPW; ++q) {
-    const int pr = wave + q * NWAVES;
-    pid[q] = pr;
-    const bool on = pr < npc;
-    pyop[q] = on ? CT.pyop[comp][pr] : 0;
-    psrc[q] = on && colok ? static_cast<const TI*>(a.f[CT.field[comp][CT.pslot[comp][pr]]])
-                          : nullptr;
-  }
-  int rowlo = P - j0, rowhi = n - j0 + P;  // rows m in [rowlo, rowhi) are inside the patch
-  rowlo = max(rowlo, 0);
-  rowhi = min(rowhi, HY);
-  const size_t cbase = size_t(gi) + size_t(n) * (j0 - P);  // only used when colok
-  auto load_col = [&](int k, int q, TI (&v)[HY]) {
+  for (int m = 0; m < HY; ++m) rows[m] = on ? min(max(j0 - P + m, 0), n - 1) * n : 0;
+  auto load_plane = [&](int k, TI (&v)[HY]) {
+    const TI* pp = fsrc + pstride * size_t(min(k, kend - 1));
 #pragma unroll
-    for (int m = 0; m < HY; ++m) {
-      v[m] = TI(0);
-      if (psrc[q] && m >= rowlo && m < rowhi) v[m] = psrc[q][cbase + size_t(m) * n + plane * size_t(k)];
+    for (int m = 0; m < HY; ++m) v[m] = (pp + rows[m])[loff];
+  };
+  // per-row coefficients of output plane te (clamped; used only when written)
+  const unsigned colo = unsigned(min(i, n - 1)) + unsigned(n) * unsigned(min(j, n - 1));
+  auto load_cf = [&](int te, TC (&c)[NCF]) {
+    const size_t po = plane * size_t(min(max(te, 0), n - 1));
+#pragma unroll
+    for (int q = 0; q < NCF; ++q) {
+      if (kQ && q == 0) c[q] = TC((a.bin[comp] + po)[colo]);
+      else if (kQ && q == 1) c[q] = TC(0);
+      else c[q] = (a.coef[q] + po)[colo];
     }
   };
 
@@ -285,112 +287,124 @@ __global__ __launch_bounds__(kRhsThreads) void rhs_kernel(RhsArgs<TC> a,
 #pragma unroll
     for (int q = 0; q < W; ++q) acc[g][q] = TC(0);
 
-  // source value at the midpoint of the substep (uniform)
+  // source value at the midpoint of the substep times this column's x and y
+  // basis values (zero for columns outside the source's support)
   double jsrc = 0.0;
-  if (kE && a.src.comp == comp) {
+  bool srccol = false;
+  if (!kQ && kE && a.src.comp == comp) {
+    const int ri = i - a.src.first[0], rj = j - a.src.first[1];
+    srccol = ri >= 0 && ri <= P && rj >= 0 && rj <= P;
     const double tm = *a.tnow + a.frac_dt;
     const double s = tm - a.src.t0;
-    jsrc = a.src.amp * sin(2.0 * 3.14159265358979323846 * a.src.f0 * s) *
-           exp(-(s / a.src.width) * (s / a.src.width));
+    const double amp = a.src.amp * sin(2.0 * 3.14159265358979323846 * a.src.f0 * s) *
+                       exp(-(s / a.src.width) * (s / a.src.width));
+    if (srccol) jsrc = amp * a.src.by[rj] * a.src.bx[ri];
   }
 
-  // ring of NPF planes of this lane's columns (input type): pre[q][0] is the next
-  TI pre[NPW][NPF][HY];
-#pragma unroll
-  for (int q = 0; q < NPW; ++q)
-#pragma unroll
-    for (int b = 0; b < NPF; ++b)
-      if (kbeg + b < kend) load_col(kbeg + b, q, pre[q][b]);
-  __syncthreads();  // band rows and z weights staged
-  for (int k = t0 - P; k < t1 + P; ++k) {
-    // coefficients of the output plane finished in this iteration, loaded
-    // before this iteration's plane prefetch so that waiting for them never
-    // waits for the prefetch
-    const int te = k - P;
-    const bool wr = te >= t0 && te < t1 && i < n && j < n;
-    const size_t o = i + size_t(n) * j + plane * te;
-    TC cf[kE ? 3 : 1];
-#pragma unroll
-    for (int q = 0; q < (kE ? 3 : 1); ++q) {
-      if (kQ && q == 0) cf[q] = wr ? TC(a.bin[comp][o]) : TC(0);
-      else if (kQ && q == 1) cf[q] = TC(0);
-      else cf[q] = wr ? a.coef[q][o] : TC(0);
-    }
-    if (k >= kbeg && k < kend) {
-      TC* G = sG + ((k - kbeg) & 1) * GSZ;
-      // y pass from registers
-#pragma unroll
-      for (int q = 0; q < NPW; ++q) {
-        if (pid[q] < npc && lane < HX) {
-          const TC* yb0 = sYB + pyop[q] * kTY * W;
-#pragma unroll
-          for (int yy = 0; yy < kTY; ++yy) {
-            TC s = TC(0);
-#pragma unroll
-            for (int d = 0; d < W; ++d) s += yb0[yy * W + d] * TC(pre[q][0][yy + d]);
-            G[(pid[q] * kTY + yy) * HX + lane] = s;
-          }
-        }
+  // write the complete output plane te (acc[.][0]) of this thread's column
+  auto emit = [&](int te, const TC (&cf)[NCF]) {
+    const unsigned o = unsigned(i) + unsigned(n) * unsigned(j);
+    const size_t po = plane * size_t(te);
+    const bool bi = (i == 0 || i == n - 1), bj = (j == 0 || j == n - 1),
+               bk = (te == 0 || te == n - 1);
+    if (kE) {
+      const TC g = cf[0], b = cf[kE ? 1 : 0], al = cf[kE ? 2 : 0];
+      TC v = kQ ? g + al * acc[2][0] : g * acc[0][0] + b * acc[1][0] + al * acc[2][0];
+      if (NG == 4) v += acc[NG - 1][0];
+      if (!kQ && srccol) {
+        const int rk = te - a.src.first[2];
+        if (rk >= 0 && rk <= P) v -= b * TC(jsrc * a.src.bz[rk]);
       }
-#pragma unroll
-      for (int q = 0; q < NPW; ++q) {
-#pragma unroll
-        for (int b = 0; b + 1 < NPF; ++b)
-#pragma unroll
-          for (int m = 0; m < HY; ++m) pre[q][b][m] = pre[q][b + 1][m];
-        if (k + NPF < kend) load_col(k + NPF, q, pre[q][NPF - 1]);
-      }
-      __syncthreads();
-      const TC* zk = sZW + (k - kbeg) * 4 * W;
-      static_for<NT>([&](auto ic) {
-        constexpr int it = decltype(ic)::value;
-        constexpr Term tm = get_term<STAGE>(it);
-        constexpr int pr = CT.term_pair[it];
-        if (tm.out == comp) {
-          TC v = TC(0);
-#pragma unroll
-          for (int d = 0; d < W; ++d) {
-            const TC xw = kXL ? sBX[(tm.x * kTX + tx) * W + d] : xb[kXL ? 0 : tm.x][d];
-            v += xw * G[(pr * kTY + ty) * HX + tx + d];
-          }
-          if (tm.sign < 0) v = -v;
-          const TC* zq = zk + tm.z * W;
-#pragma unroll
-          for (int q = 0; q < W; ++q) acc[tm.grp][q] += zq[q] * v;
-        }
-      });
+      // E_c is constrained on the faces normal to the two other axes
+      const bool bnd = (comp == 0) ? (bj || bk) : (comp == 1) ? (bi || bk) : (bi || bj);
+      (static_cast<TO*>(a.out[comp]) + po)[o] = bnd ? TO(0) : TO(v);
+      if (a.out2[comp]) (static_cast<float*>(a.out2[comp]) + po)[o] = bnd ? 0.0f : float(v);
+    } else {
+      const TC v = acc[0][0] + cf[0] * acc[1][0];
+      // H_c is constrained on the faces normal to axis c
+      const bool bnd = (comp == 0) ? bi : (comp == 1) ? bj : bk;
+      (static_cast<TO*>(a.out[comp]) + po)[o] = bnd ? TO(0) : TO(v);
     }
-    if (te >= t0 && te < t1) {
-      if (i < n && j < n) {
-        const bool bi = (i == 0 || i == n - 1), bj = (j == 0 || j == n - 1),
-                   bk = (te == 0 || te == n - 1);
-        if (kE) {
-          const TC g = cf[0], b = cf[1], al = cf[kE ? 2 : 0];
-          TC v = kQ ? g + al * acc[2][0] : g * acc[0][0] + b * acc[1][0] + al * acc[2][0];
-          if (NG == 4) v += acc[NG - 1][0];
-          if (!kQ && comp == a.src.comp) {
-            const int ri = i - a.src.first[0], rj = j - a.src.first[1], rk = te - a.src.first[2];
-            if (ri >= 0 && ri <= P && rj >= 0 && rj <= P && rk >= 0 && rk <= P)
-              v -= b * TC(jsrc * (a.src.bz[rk] * a.src.by[rj] * a.src.bx[ri]));
-          }
-          // E_c is constrained on the faces normal to the two other axes
-          const bool bnd = (comp == 0) ? (bj || bk) : (comp == 1) ? (bi || bk) : (bi || bj);
-          static_cast<TO*>(a.out[comp])[o] = bnd ? TO(0) : TO(v);
-          if (a.out2[comp]) static_cast<float*>(a.out2[comp])[o] = bnd ? 0.0f : float(v);
-        } else {
-          const TC v = acc[0][0] + cf[0] * acc[1][0];
-          // H_c is constrained on the faces normal to axis c
-          const bool bnd = (comp == 0) ? bi : (comp == 1) ? bj : bk;
-          static_cast<TO*>(a.out[comp])[o] = bnd ? TO(0) : TO(v);
-        }
-      }
-    }
+  };
+  auto shift = [&]() {
 #pragma unroll
     for (int g = 0; g < NG; ++g) {
 #pragma unroll
       for (int q = 0; q < W - 1; ++q) acc[g][q] = acc[g][q + 1];
       acc[g][W - 1] = TC(0);
     }
+  };
+  const bool inplane = i < n && j < n;
+
+  // Input plane k (kbeg <= k < kend) is held in ring slot (k - kbeg) & 1 and
+  // its y-pass result in LDS buffer (k - kbeg) & 1; the loop is unrolled by
+  // two so that both slots are static registers (no copies, which would wait
+  // for the loads in flight).  Plane k + 2 is loaded into the slot as soon
+  // as plane k has been consumed, and the coefficients of an output plane
+  // one iteration before it is written.
+  TI pre[2][HY];
+  TC cfr[2][NCF];
+  load_plane(kbeg, pre[0]);
+  load_plane(kbeg + 1, pre[1]);
+  load_cf(kbeg - P, cfr[0]);
+  __syncthreads();  // band rows and z weights staged
+  auto body = [&](auto sc, int k) {
+    constexpr int S = decltype(sc)::value;
+    const int te = k - P;
+    load_cf(te + 1, cfr[S ^ 1]);
+    TC* G = sG + S * GSZ;
+    // y pass from registers
+    if (on && lane < HX) {
+      const TC* yb0 = sYB + pyop * kTY * W;
+#pragma unroll
+      for (int yy = 0; yy < kTY; ++yy) {
+        TC s = TC(0);
+#pragma unroll
+        for (int d = 0; d < W; ++d) s += yb0[yy * W + d] * TC(pre[S][yy + d]);
+        G[(wave * kTY + yy) * HX + lane] = s;
+      }
+    }
+    load_plane(k + 2, pre[S]);
+    __syncthreads();
+    const TC* zk = sZW + (k - kbeg) * 4 * W;
+    static_for<NT>([&](auto ic) {
+      constexpr int it = decltype(ic)::value;
+      constexpr Term tm = get_term<STAGE>(it);
+      constexpr int tp = CT.term_pair[it];
+      if (tm.out == comp) {
+        TC v = TC(0);
+#pragma unroll
+        for (int d = 0; d < W; ++d) {
+          const TC xw = kXL ? sBX[(tm.x * kTX + tx) * W + d] : xb[kXL ? 0 : tm.x][d];
+          v += xw * G[(tp * kTY + ty) * HX + tx + d];
+        }
+        if (tm.sign < 0) v = -v;
+        const TC* zq = zk + tm.z * W;
+#pragma unroll
+        for (int q = 0; q < W; ++q) acc[tm.grp][q] += zq[q] * v;
+      }
+    });
+    if (te >= t0 && te < t1 && inplane) emit(te, cfr[S]);
+    shift();
+  };
+  int k = kbeg;
+  for (; k + 1 < kend; k += 2) {
+    body(std::integral_constant<int, 0>{}, k);
+    body(std::integral_constant<int, 1>{}, k + 1);
+  }
+  if (k < kend) {
+    body(std::integral_constant<int, 0>{}, k);
+    ++k;
+  }
+  // output planes past the last input plane (top of the grid)
+  for (; k < t1 + P; ++k) {
+    const int te = k - P;
+    if (te >= t0 && te < t1 && inplane) {
+      TC c[NCF];
+      load_cf(te, c);
+      emit(te, c);
+    }
+    shift();
   }
 }
 
