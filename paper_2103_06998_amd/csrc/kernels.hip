@@ -435,6 +435,10 @@ __device__ __forceinline__ void stage_batched(T* dst, const T* __restrict__ src,
 template <typename T>
 struct SweepLoadRows { static constexpr int value = sizeof(T) == 8 ? 32 : 64; };
 constexpr int kCH = 8;       // rows per compute chunk of the LDS part
+// register slots of per-line factor chunks (float64: two, as its register
+// rows leave no room for a third without spilling)
+template <typename T, int P>
+constexpr int fac_ring() { return sizeof(T) == 8 ? 2 : 3; }
 
 // Rows of a line kept in registers (the rest in LDS): float64 tiles would
 // limit a CU to two waves by LDS alone, so their first 72 rows stay in
@@ -603,20 +607,25 @@ __global__ __launch_bounds__(64) void sweep_kernel(SweepArgs a) {
     h[0] = s;
     yr[r] = s;
   }
-  // ---- forward, LDS rows.  Per-line factors (global memory) of the next
-  // chunk are loaded while the current chunk is computed.
+  // ---- forward, LDS rows.  Shared factors come from LDS.  Per-line factors
+  // (global memory) go through a ring of kD register slots of kCH rows: the
+  // loads of chunk j + kD - 1 are issued before chunk j is computed, all
+  // unconditionally (rows clamped), and the chunk loop is unrolled by the
+  // ring length so that every slot is a fixed set of registers; a wave so
+  // keeps kD - 1 chunks of factors in flight.
+  constexpr int kD = MOD ? fac_ring<T, P>() : 1;
+  const int nch = n > kRR ? (n - kRR + kCH - 1) / kCH : 0;  // chunks of LDS rows
   {
-    T f[kCH][P];
-    auto load_f = [&](int r0, T (&g)[kCH][P]) {
+    T f[kD][kCH][P];
+    auto load_f = [&](int j, T (&g)[kCH][P]) {
+      const int r0 = kRR + j * kCH;
 #pragma unroll
       for (int c = 0; c < kCH; ++c)
 #pragma unroll
         for (int k = 0; k < P; ++k) g[c][k] = fL(min(r0 + c, n - 1), k);
     };
-    if (kRR < n) load_f(kRR, f);
-    for (int r0 = kRR; r0 < n; r0 += kCH) {
-      T fn[kCH][P];
-      if (MOD && r0 + kCH < n) load_f(r0 + kCH, fn);
+    auto fwd_chunk = [&](int j, const T (&g)[kCH][P]) {
+      const int r0 = kRR + j * kCH;
       T v[kCH];
 #pragma unroll
       for (int c = 0; c < kCH; ++c) v[c] = buf[(min(r0 + c, n - 1) - kRR) * PIT + lane];
@@ -624,7 +633,7 @@ __global__ __launch_bounds__(64) void sweep_kernel(SweepArgs a) {
       for (int c = 0; c < kCH; ++c) {
         T s = v[c];
 #pragma unroll
-        for (int k = P - 1; k >= 0; --k) s -= f[c][k] * h[k];
+        for (int k = P - 1; k >= 0; --k) s -= g[c][k] * h[k];
 #pragma unroll
         for (int k = P - 1; k > 0; --k) h[k] = h[k - 1];
         h[0] = s;
@@ -633,24 +642,35 @@ __global__ __launch_bounds__(64) void sweep_kernel(SweepArgs a) {
 #pragma unroll
       for (int c = 0; c < kCH; ++c)
         if (r0 + c < n) buf[(r0 + c - kRR) * PIT + lane] = v[c];
-      if (r0 + kCH < n) {
-        if (MOD) {
+    };
+    if (MOD) {
+      if (nch > 0) {
 #pragma unroll
-          for (int c = 0; c < kCH; ++c)
-#pragma unroll
-            for (int k = 0; k < P; ++k) f[c][k] = fn[c][k];
-        } else {
-          load_f(r0 + kCH, f);
+        for (int s = 0; s + 1 < kD; ++s) load_f(s, f[s]);
+        for (int j0 = 0; j0 < nch; j0 += kD) {
+          static_for<kD>([&](auto sc) {
+            constexpr int S = decltype(sc)::value;
+            const int j = j0 + S;
+            load_f(j + kD - 1, f[(S + kD - 1) % kD]);
+            if (j < nch) fwd_chunk(j, f[S]);  // uniform
+          });
         }
+      }
+    } else {
+      for (int j = 0; j < nch; ++j) {
+        load_f(j, f[0]);
+        fwd_chunk(j, f[0]);
       }
     }
   }
-  // ---- backward, LDS rows (from the last row down to kRR)
+  // ---- backward, LDS rows (from the last row down to kRR), same ring
 #pragma unroll
   for (int k = 0; k < P; ++k) h[k] = T(0);
   {
-    T f[kCH][P], d[kCH];
-    auto load_f = [&](int r0, T (&g)[kCH][P], T (&e)[kCH]) {
+    T f[kD][kCH][P], d[kD][kCH];
+    // chunk j holds rows n-1-j*kCH, n-2-j*kCH, ... (descending, clamped at kRR)
+    auto load_f = [&](int j, T (&g)[kCH][P], T (&e)[kCH]) {
+      const int r0 = n - 1 - j * kCH;
 #pragma unroll
       for (int c = 0; c < kCH; ++c) {
         const int rf = max(r0 - c, kRR);
@@ -659,19 +679,17 @@ __global__ __launch_bounds__(64) void sweep_kernel(SweepArgs a) {
         e[c] = fD(rf);
       }
     };
-    if (n - 1 >= kRR) load_f(n - 1, f, d);
-    for (int r0 = n - 1; r0 >= kRR; r0 -= kCH) {
-      T fn[kCH][P], dn[kCH];
-      if (MOD && r0 - kCH >= kRR) load_f(r0 - kCH, fn, dn);
+    auto bwd_chunk = [&](int j, const T (&g)[kCH][P], const T (&e)[kCH]) {
+      const int r0 = n - 1 - j * kCH;
       T v[kCH];
 #pragma unroll
       for (int c = 0; c < kCH; ++c) v[c] = buf[(max(r0 - c, kRR) - kRR) * PIT + lane];
 #pragma unroll
       for (int c = 0; c < kCH; ++c) {
         if (r0 - c >= kRR) {  // uniform
-          T s = d[c] * v[c];
+          T s = e[c] * v[c];
 #pragma unroll
-          for (int k = P - 1; k >= 0; --k) s -= f[c][k] * h[k];
+          for (int k = P - 1; k >= 0; --k) s -= g[c][k] * h[k];
 #pragma unroll
           for (int k = P - 1; k > 0; --k) h[k] = h[k - 1];
           h[0] = s;
@@ -681,32 +699,76 @@ __global__ __launch_bounds__(64) void sweep_kernel(SweepArgs a) {
 #pragma unroll
       for (int c = 0; c < kCH; ++c)
         if (r0 - c >= kRR) buf[(r0 - c - kRR) * PIT + lane] = v[c];
-      if (r0 - kCH >= kRR) {
-        if (MOD) {
+    };
+    if (MOD) {
+      if (nch > 0) {
 #pragma unroll
-          for (int c = 0; c < kCH; ++c) {
-#pragma unroll
-            for (int k = 0; k < P; ++k) f[c][k] = fn[c][k];
-            d[c] = dn[c];
-          }
-        } else {
-          load_f(r0 - kCH, f, d);
+        for (int s = 0; s + 1 < kD; ++s) load_f(s, f[s], d[s]);
+        for (int j0 = 0; j0 < nch; j0 += kD) {
+          static_for<kD>([&](auto sc) {
+            constexpr int S = decltype(sc)::value;
+            const int j = j0 + S;
+            load_f(j + kD - 1, f[(S + kD - 1) % kD], d[(S + kD - 1) % kD]);
+            if (j < nch) bwd_chunk(j, f[S], d[S]);  // uniform
+          });
         }
+      }
+    } else {
+      for (int j = 0; j < nch; ++j) {
+        load_f(j, f[0], d[0]);
+        bwd_chunk(j, f[0], d[0]);
       }
     }
   }
-  // ---- backward, register rows (padding rows r >= n are skipped)
+  // ---- backward, register rows (padding rows r >= n are skipped).  Per-line
+  // factors of a chunk of kCH rows are loaded, unconditionally (rows
+  // clamped), while the chunk before it is computed; a load inside the
+  // per-row branch would be waited for row by row.
+  if (!MOD || P < 3) {
 #pragma unroll
-  for (int r = kRR - 1; r >= 0; --r) {
-    if (r < n) {  // uniform
-      T s = fD(r) * yr[r];
+    for (int r = kRR - 1; r >= 0; --r) {
+      if (r < n) {  // uniform
+        T s = fD(r) * yr[r];
 #pragma unroll
-      for (int k = P - 1; k >= 0; --k) s -= fU(r, k) * h[k];
+        for (int k = P - 1; k >= 0; --k) s -= fU(r, k) * h[k];
 #pragma unroll
-      for (int k = P - 1; k > 0; --k) h[k] = h[k - 1];
-      h[0] = s;
-      yr[r] = s;
+        for (int k = P - 1; k > 0; --k) h[k] = h[k - 1];
+        h[0] = s;
+        yr[r] = s;
+      }
     }
+  } else if (kRR > 0) {
+    constexpr int NRC = (kRR + kCH - 1) / kCH;
+    T gu[2][kCH][P], gd[2][kCH];
+    auto load_r = [&](int q, T (&g)[kCH][P], T (&e)[kCH]) {
+#pragma unroll
+      for (int c = 0; c < kCH; ++c) {
+        const int rf = min(max(kRR - 1 - q * kCH - c, 0), n - 1);
+#pragma unroll
+        for (int k = 0; k < P; ++k) g[c][k] = fU(rf, k);
+        e[c] = fD(rf);
+      }
+    };
+    load_r(0, gu[0], gd[0]);
+    static_for<NRC>([&](auto qc) {
+      constexpr int q = decltype(qc)::value;
+      if (q + 1 < NRC) load_r(q + 1, gu[(q + 1) & 1], gd[(q + 1) & 1]);
+#pragma unroll
+      for (int c = 0; c < kCH; ++c) {
+        constexpr int r0 = kRR - 1 - q * kCH;
+        const int r = r0 - c;
+        if (r >= 0 && r < n) {  // uniform
+          T s = gd[q & 1][c] * yr[r];
+#pragma unroll
+          for (int k = P - 1; k >= 0; --k) s -= gu[q & 1][c][k] * h[k];
+#pragma unroll
+          for (int k = P - 1; k > 0; --k) h[k] = h[k - 1];
+          h[0] = s;
+          yr[r] = s;
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);  // keep each chunk's loads in its slot
+    });
   }
 
   // ---- store
