@@ -441,10 +441,12 @@ template <typename T, int P>
 constexpr int fac_ring() { return sizeof(T) == 8 ? 2 : 3; }
 
 // Rows of a line kept in registers (the rest in LDS): float64 tiles would
-// limit a CU to two waves by LDS alone, so their first 72 rows stay in
-// registers; float32 tiles fit four waves per CU entirely in LDS.
-template <typename T>
-struct SweepRegRows { static constexpr int value = sizeof(T) == 8 ? 72 : 0; };
+// limit a CU to two waves by LDS alone, so their first rows stay in
+// registers (72 for shared factors; 40 for per-line factors, whose
+// prefetch slots need the registers and whose launches have at most a few
+// waves per CU); float32 tiles fit four waves per CU entirely in LDS.
+template <typename T, bool MOD>
+struct SweepRegRows { static constexpr int value = sizeof(T) == 8 ? (MOD ? 40 : 72) : 0; };
 
 __host__ __device__ constexpr int sweep_pitch(bool xax) { return xax ? 65 : 64; }
 
@@ -469,7 +471,7 @@ template <typename T, int P, bool XAX, bool MOD>
 __global__ __launch_bounds__(64) void sweep_kernel(SweepArgs a) {
   constexpr int kLoadCH = SweepLoadRows<T>::value;
   constexpr int PIT = sweep_pitch(XAX);
-  constexpr int kRR = SweepRegRows<T>::value;
+  constexpr int kRR = SweepRegRows<T, MOD>::value;
   constexpr int kRA = kRR > 0 ? kRR : 1;  // register array extent
   extern __shared__ __align__(16) unsigned char smem[];
   T* buf = reinterpret_cast<T*>(smem);
@@ -595,17 +597,51 @@ __global__ __launch_bounds__(64) void sweep_kernel(SweepArgs a) {
   T h[P];
 #pragma unroll
   for (int k = 0; k < P; ++k) h[k] = T(0);
-  // ---- forward, register rows (rows >= n are padding and never stored)
+  // ---- forward, register rows (rows >= n are padding and never stored).
+  // Per-line factors: a chunk's loads are issued while the chunk before it
+  // is computed (two fixed register slots, unconditional clamped loads).
+  if (!MOD || P < 3) {
 #pragma unroll
-  for (int r = 0; r < kRR; ++r) {
-    const int rf = min(r, n - 1);
-    T s = yr[r];
+    for (int r = 0; r < kRR; ++r) {
+      const int rf = min(r, n - 1);
+      T s = yr[r];
 #pragma unroll
-    for (int k = P - 1; k >= 0; --k) s -= fL(rf, k) * h[k];
+      for (int k = P - 1; k >= 0; --k) s -= fL(rf, k) * h[k];
 #pragma unroll
-    for (int k = P - 1; k > 0; --k) h[k] = h[k - 1];
-    h[0] = s;
-    yr[r] = s;
+      for (int k = P - 1; k > 0; --k) h[k] = h[k - 1];
+      h[0] = s;
+      yr[r] = s;
+    }
+  } else if (kRR > 0) {
+    constexpr int NRC = (kRR + kCH - 1) / kCH;
+    T gl[2][kCH][P];
+    auto load_r = [&](int q, T (&g)[kCH][P]) {
+#pragma unroll
+      for (int c = 0; c < kCH; ++c) {
+        const int rf = min(q * kCH + c, n - 1);
+#pragma unroll
+        for (int k = 0; k < P; ++k) g[c][k] = fL(rf, k);
+      }
+    };
+    load_r(0, gl[0]);
+    static_for<NRC>([&](auto qc) {
+      constexpr int q = decltype(qc)::value;
+      if (q + 1 < NRC) load_r(q + 1, gl[(q + 1) & 1]);
+#pragma unroll
+      for (int c = 0; c < kCH; ++c) {
+        constexpr int r0 = q * kCH;
+        if (r0 + c < kRR) {
+          T s = yr[r0 + c];
+#pragma unroll
+          for (int k = P - 1; k >= 0; --k) s -= gl[q & 1][c][k] * h[k];
+#pragma unroll
+          for (int k = P - 1; k > 0; --k) h[k] = h[k - 1];
+          h[0] = s;
+          yr[r0 + c] = s;
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);  // keep each chunk's loads in its slot
+    });
   }
   // ---- forward, LDS rows.  Shared factors come from LDS.  Per-line factors
   // (global memory) go through a ring of kD register slots of kCH rows: the
@@ -1149,7 +1185,7 @@ hipError_t launch_rhs_any(int stage, int p, const RhsArgs<TC>& a, hipStream_t s)
 
 template <typename T, int P, bool XAX, bool MOD>
 hipError_t launch_sweep_k(int ndesc, const SweepArgs& a, hipStream_t s) {
-  const size_t lds = (size_t(sweep_buf_rows(a.n, XAX, SweepRegRows<T>::value)) * sweep_pitch(XAX) +
+  const size_t lds = (size_t(sweep_buf_rows(a.n, XAX, SweepRegRows<T, MOD>::value)) * sweep_pitch(XAX) +
                       (MOD ? 0 : size_t(a.n) * (2 * P + 1))) * sizeof(T);
   dim3 grid((a.nlines + 63) / 64, ndesc);
   auto k = sweep_kernel<T, P, XAX, MOD>;
