@@ -155,7 +155,8 @@ int adi_sync(adi_ctx* ctx);
  * launch's duration (the state advances by nsteps steps).  adi_profile_read
  * reports, for each launch of a step in launch order: its kind (0 = E
  * right-hand side, 1 = H right-hand side, 2 = float64 residual, 3 = x-line
- * solves, 4 = y/z-line solves), the number of field components it processes,
+ * solves, 4 = y/z-line solves, 5 = x- and y/z-line solves of one round in
+ * one launch), the number of field components it processes,
  * how many of those use per-line (material-modified) factors, and its mean
  * duration in milliseconds.  *nout receives the number of launches per step
  * (the arrays hold cap entries).

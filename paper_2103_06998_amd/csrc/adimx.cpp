@@ -215,7 +215,8 @@ int pick_zchunk(int n) {
 }
 
 // ---------------------------------------------------------------- enqueue
-enum LaunchKind { kKindRhsE = 0, kKindRhsH = 1, kKindResidual = 2, kKindSweepX = 3, kKindSweepYZ = 4 };
+enum LaunchKind { kKindRhsE = 0, kKindRhsH = 1, kKindResidual = 2, kKindSweepX = 3, kKindSweepYZ = 4,
+                  kKindSweepXYZ = 5 };
 
 // Run `launch` on stream s; when profiling, bracket it with two events.
 template <typename F>
@@ -350,6 +351,26 @@ hipError_t enqueue_solves(adi_ctx* c, int kindH, int sub, void* buf, void* final
       int nmod = 0;
       for (int q = 0; q < nd[xgroup]; ++q) nmod += a.d[q].modified;
       a.spike = (c->spike_ok && nmod == 0) ? 1 : 0;
+    }
+    // x and y/z descriptors of one kind (all modified or all shared) whose
+    // blocks fit about one block per SIMD: one launch, x descriptors first
+    // (no cross-stream fork and join, which cost 5-9 us per round); larger
+    // rounds run better as two concurrent launches
+    const size_t blocks = size_t((c->n * c->n + 63) / 64) * size_t(nd[0] + nd[1]);
+    if (nd[0] > 0 && nd[1] > 0 && blocks <= 1024) {
+      const int nmod0 = [&] { int m = 0; for (int q = 0; q < nd[0]; ++q) m += grp[0].d[q].modified; return m; }();
+      const int nmod1 = [&] { int m = 0; for (int q = 0; q < nd[1]; ++q) m += grp[1].d[q].modified; return m; }();
+      const int nall = nd[0] + nd[1], mall = nmod0 + nmod1;
+      if (mall == 0 || mall == nall) {
+        SweepArgs a = grp[1];
+        for (int q = 0; q < nd[0]; ++q) a.d[nd[1] + q] = grp[0].d[q];
+        a.xaxis = 2;
+        a.spike = (c->spike_ok && mall == 0) ? 1 : 0;
+        hipError_t e = timed(c, s, kKindSweepXYZ, nall, mall,
+                             [&] { return launch_sweep<T>(c->p, nall, a, s); });
+        if (e != hipSuccess) return e;
+        continue;
+      }
     }
     const bool branch = nd[0] > 0 && nd[1] > 0 && !c->profiling && c->side;
     hipEvent_t ev = nullptr;

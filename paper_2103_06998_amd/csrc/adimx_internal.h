@@ -104,7 +104,8 @@ struct SweepArgs {
   SweepDesc d[3];         // blockIdx.y selects the descriptor
   int n;
   int nlines;
-  int xaxis;              // 1: all descriptors are x lines (transposing kernel)
+  int xaxis;              // 0: y/z lines, 1: x lines (transposing kernel),
+                          // 2: both, descriptors of x lines first
   int spike;              // 1: shared-factor lines solved in kSpikeS segments each
   double* tick_t;         // if non-null, block (0,0) thread 0 does *tick_t += tick_dt
   double tick_dt;

@@ -5,6 +5,7 @@
 // the paper's reordering of a right-hand side into N_x-long rows.
 #include "adimx_internal.h"
 
+#include <algorithm>
 #include <type_traits>
 #include <utility>
 
@@ -468,7 +469,7 @@ __host__ __device__ inline int sweep_buf_rows(int n, bool xax, int rr) {
 // adds one dependent FMA.  Shared factors [r*P + k] / [r] are staged in LDS;
 // per-line factors are read as [((l/64 * n + r) * P + k) * 64 + l%64].
 template <typename T, int P, bool XAX, bool MOD>
-__global__ __launch_bounds__(64) void sweep_kernel(SweepArgs a) {
+__device__ __forceinline__ void sweep_body(const SweepArgs& a) {
   constexpr int kLoadCH = SweepLoadRows<T>::value;
   constexpr int PIT = sweep_pitch(XAX);
   constexpr int kRR = SweepRegRows<T, MOD>::value;
@@ -853,7 +854,7 @@ __global__ __launch_bounds__(64) void sweep_kernel(SweepArgs a) {
 // The factors, spikes and R of the descriptor are staged in LDS (broadcast
 // reads: every lane of a wave reads the same row).
 template <typename T, int P, bool XAX, int MR>
-__global__ __launch_bounds__(64 * kSpikeS) void spike_kernel(SweepArgs a) {
+__device__ __forceinline__ void spike_body(const SweepArgs& a) {
   constexpr int S = kSpikeS, Q = 2 * P * (S - 1);
   extern __shared__ __align__(16) unsigned char smem[];
   T* sf = reinterpret_cast<T*>(smem);
@@ -1037,6 +1038,30 @@ __global__ __launch_bounds__(64 * kSpikeS) void spike_kernel(SweepArgs a) {
   if (a.tick_t && blockIdx.x == 0 && blockIdx.y == 0 && tid == 0) *a.tick_t += a.tick_dt;
 }
 
+// Kernels of the two line solvers.  A solve round whose descriptors mix x
+// lines with y/z lines runs as one launch (the descriptor's axis selects the
+// code path per block, x descriptors first so that the longer x blocks start
+// first) instead of two launches on two streams joined by events: the
+// cross-stream waits left the GPU idle for 5-9 us per round.
+template <typename T, int P, bool XAX, bool MOD>
+__global__ __launch_bounds__(64) void sweep_kernel(SweepArgs a) {
+  sweep_body<T, P, XAX, MOD>(a);
+}
+template <typename T, int P, bool MOD>
+__global__ __launch_bounds__(64) void sweep_mixed_kernel(SweepArgs a) {
+  if (a.d[blockIdx.y].axis == 0) sweep_body<T, P, true, MOD>(a);
+  else sweep_body<T, P, false, MOD>(a);
+}
+template <typename T, int P, bool XAX, int MR>
+__global__ __launch_bounds__(64 * kSpikeS) void spike_kernel(SweepArgs a) {
+  spike_body<T, P, XAX, MR>(a);
+}
+template <typename T, int P, int MR>
+__global__ __launch_bounds__(64 * kSpikeS) void spike_mixed_kernel(SweepArgs a) {
+  if (a.d[blockIdx.y].axis == 0) spike_body<T, P, true, MR>(a);
+  else spike_body<T, P, false, MR>(a);
+}
+
 // ------------------------------------------------------------ factorisation
 // Pivot-free banded Doolittle LU of the material-modified 1D matrices, one
 // line per thread, in float64.  Row r of line l is Mb[r,:] + alpha[pos] Sb[r,:]
@@ -1184,11 +1209,25 @@ hipError_t launch_rhs_any(int stage, int p, const RhsArgs<TC>& a, hipStream_t s)
 }
 
 template <typename T, int P, bool XAX, bool MOD>
+size_t sweep_lds(int n) {
+  return (size_t(sweep_buf_rows(n, XAX, SweepRegRows<T, MOD>::value)) * sweep_pitch(XAX) +
+          (MOD ? 0 : size_t(n) * (2 * P + 1))) * sizeof(T);
+}
+template <typename T, int P, bool XAX, bool MOD>
 hipError_t launch_sweep_k(int ndesc, const SweepArgs& a, hipStream_t s) {
-  const size_t lds = (size_t(sweep_buf_rows(a.n, XAX, SweepRegRows<T, MOD>::value)) * sweep_pitch(XAX) +
-                      (MOD ? 0 : size_t(a.n) * (2 * P + 1))) * sizeof(T);
+  const size_t lds = sweep_lds<T, P, XAX, MOD>(a.n);
   dim3 grid((a.nlines + 63) / 64, ndesc);
   auto k = sweep_kernel<T, P, XAX, MOD>;
+  hipError_t e = set_lds(k, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k, grid, dim3(64), lds, s, a);
+  return hipGetLastError();
+}
+template <typename T, int P, bool MOD>
+hipError_t launch_sweep_mixed(int ndesc, const SweepArgs& a, hipStream_t s) {
+  const size_t lds = std::max(sweep_lds<T, P, true, MOD>(a.n), sweep_lds<T, P, false, MOD>(a.n));
+  dim3 grid((a.nlines + 63) / 64, ndesc);
+  auto k = sweep_mixed_kernel<T, P, MOD>;
   hipError_t e = set_lds(k, lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k, grid, dim3(64), lds, s, a);
@@ -1208,12 +1247,33 @@ hipError_t launch_spike_k(int ndesc, const SweepArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <typename T, int P, bool XAX>
-hipError_t launch_spike_x(int ndesc, const SweepArgs& a, hipStream_t s) {
+template <typename T, int P, int MR>
+hipError_t launch_spike_mixed_k(int ndesc, const SweepArgs& a, hipStream_t s) {
+  constexpr int Q = 2 * P * (kSpikeS - 1);
+  const size_t lds = (size_t(a.n) * (4 * P + 1) + Q * Q + size_t(Q) * 64 +
+                      size_t(kSpikeS) * 8 * 65) * sizeof(T);
+  dim3 grid((a.nlines + 63) / 64, ndesc);
+  auto k = spike_mixed_kernel<T, P, MR>;
+  hipError_t e = set_lds(k, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k, grid, dim3(64 * kSpikeS), lds, s, a);
+  return hipGetLastError();
+}
+// xaxis: 0 = y/z lines, 1 = x lines, 2 = both (descriptor axis per block)
+template <typename T, int P>
+hipError_t launch_spike_x(int xaxis, int ndesc, const SweepArgs& a, hipStream_t s) {
   // register rows per segment: ceil(n / kSpikeS)
   const int m = (a.n + kSpikeS - 1) / kSpikeS;
-  if (m <= 40) return launch_spike_k<T, P, XAX, 40>(ndesc, a, s);
-  if (m <= 72) return launch_spike_k<T, P, XAX, 72>(ndesc, a, s);
+  if (m <= 40) {
+    if (xaxis == 2) return launch_spike_mixed_k<T, P, 40>(ndesc, a, s);
+    return xaxis ? launch_spike_k<T, P, true, 40>(ndesc, a, s)
+                 : launch_spike_k<T, P, false, 40>(ndesc, a, s);
+  }
+  if (m <= 72) {
+    if (xaxis == 2) return launch_spike_mixed_k<T, P, 72>(ndesc, a, s);
+    return xaxis ? launch_spike_k<T, P, true, 72>(ndesc, a, s)
+                 : launch_spike_k<T, P, false, 72>(ndesc, a, s);
+  }
   return hipErrorInvalidValue;
 }
 
@@ -1227,9 +1287,11 @@ hipError_t launch_sweep_p(int ndesc, const SweepArgs& a, hipStream_t s) {
     if (a.n < kSpikeMinN || a.n > kSpikeMaxN) return hipErrorInvalidValue;
     for (int i = 0; i < ndesc; ++i)
       if (!a.d[i].spk) return hipErrorInvalidValue;
-    return a.xaxis ? launch_spike_x<T, P, true>(ndesc, a, s)
-                   : launch_spike_x<T, P, false>(ndesc, a, s);
+    return launch_spike_x<T, P>(a.xaxis, ndesc, a, s);
   }
+  if (a.xaxis == 2)
+    return mod ? launch_sweep_mixed<T, P, true>(ndesc, a, s)
+               : launch_sweep_mixed<T, P, false>(ndesc, a, s);
   if (a.xaxis)
     return mod ? launch_sweep_k<T, P, true, true>(ndesc, a, s)
                : launch_sweep_k<T, P, true, false>(ndesc, a, s);

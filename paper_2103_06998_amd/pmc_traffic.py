@@ -33,6 +33,8 @@ def kernel_class(name: str):
         stage = int(m.group(1))
         return {0: "rhs_E", 1: "rhs_E", 2: "rhs_H", 3: "rhs_H", 6: "residual64",
                 7: "residual64"}.get(stage)
+    if re.search(r"(sweep|spike)_mixed_kernel<", name):
+        return "sweep_xyz"
     m = re.search(r"(sweep|spike)_kernel<\w+, \d+, (true|false)", name)
     if m:
         return "sweep_x" if m.group(2) == "true" else "sweep_yz"
