@@ -137,6 +137,26 @@ def test_full_steps_random_material(Solver, N, p, steps):
     compare_state(got, E, H, TOL64, (N, p))
 
 
+@pytest.mark.parametrize("precision,tol", [("fp64", TOL64), ("fp32_refine", TOL32)])
+def test_large_rounds_two_launches(Solver, precision, tol):
+    """n = 148: a solve round's x and y/z lines (3 x 343 blocks of 64 lines)
+    exceed the single-launch limit of 1024 blocks, so each round runs as two
+    concurrent launches joined by events (smaller grids take one mixed-axis
+    launch); one step against the oracle."""
+    N, p = 146, 2
+    eps, mu, sig, src = random_setup(N, p, seed=7)
+    dt = 0.5 / N
+    prob = maxwell.Problem(N, p, eps, mu, sig, dt, src)
+    s = make_gpu(Solver, N, p, eps, mu, sig, dt, src, precision)
+    E, H = constrained_random_state(prob, 13)
+    t = 0.02
+    s.set_fields(np.stack(E + H), t)
+    s.step(1)
+    E, H, t = prob.run(E, H, t, 1)
+    got, _ = s.get_fields()
+    compare_state(got, E, H, tol, ("n148", precision))
+
+
 def test_mms16_manufactured_solution(Solver):
     """16^3 p=2, eps = mu = 1, u_A initial state, 10 steps of 1e-3 (FP64)."""
     w = workloads.make("mms16")
