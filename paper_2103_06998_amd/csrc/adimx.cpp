@@ -352,10 +352,10 @@ hipError_t enqueue_solves(adi_ctx* c, int kindH, int sub, void* buf, void* final
       for (int q = 0; q < nd[xgroup]; ++q) nmod += a.d[q].modified;
       a.spike = (c->spike_ok && nmod == 0) ? 1 : 0;
     }
-    // x and y/z descriptors of one kind (all modified or all shared) whose
-    // blocks fit about one block per SIMD: one launch, x descriptors first
-    // (no cross-stream fork and join, which cost 5-9 us per round); larger
-    // rounds run better as two concurrent launches
+    // x and y/z descriptors of one kind (all modified or all shared), with
+    // at most 1024 blocks of 64 lines in all: one launch, x descriptors
+    // first (no cross-stream fork and join, which cost 5-9 us per round);
+    // larger rounds run better as two concurrent launches
     const size_t blocks = size_t((c->n * c->n + 63) / 64) * size_t(nd[0] + nd[1]);
     if (nd[0] > 0 && nd[1] > 0 && blocks <= 1024) {
       const int nmod0 = [&] { int m = 0; for (int q = 0; q < nd[0]; ++q) m += grp[0].d[q].modified; return m; }();
