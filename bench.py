@@ -128,11 +128,17 @@ def run_gpu(precision, w, steps, warmup):
     b = kinds[dom]
     per_launch_bytes = b["bytes"] / b["launches"]
     achieved = per_launch_bytes / (b["avg_ms"] * 1e-3) / 1e9
+    # per-line factors streamed by the class's material-modified launches
+    # ((2p+1) words per row: L, D*U, D): in the counter traffic, not in the
+    # algorithmic bytes
+    dom_launches = [L for L in launches if L["kind"] == dom]
+    factor_bytes = sum(L["nmod"] * (2 * w.p + 1) * D * wbytes for L in dom_launches)
     roofline = {
         "bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
         "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
         "traffic": traffic_from_profiles(dom, precision),
         "bytes_per_launch": int(per_launch_bytes), "avg_launch_ms": round(b["avg_ms"], 5),
+        "factor_bytes_per_launch": int(factor_bytes / max(1, len(dom_launches))),
     }
     step_bytes = sum(algorithmic_bytes(L, D, wbytes, refine) for L in launches)
     kernel_ms = sum(L["ms"] for L in launches)
