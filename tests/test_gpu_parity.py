@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 import workloads
-from oracle import maxwell, mms
+from oracle import gram, maxwell, mms
 
 pytestmark = pytest.mark.gpu
 
@@ -65,7 +65,7 @@ def compare_state(EH_gpu, E, H, tol, label=""):
     return errs
 
 
-@pytest.mark.parametrize("N,p", [(1, 1), (2, 2), (5, 1), (5, 2), (4, 3), (7, 3)])
+@pytest.mark.parametrize("N,p", [(1, 1), (2, 2), (5, 1), (5, 2), (4, 3), (7, 3), (3, 4), (9, 4)])
 @pytest.mark.parametrize("stage,sub", [(0, 1), (0, 2), (1, 1), (1, 2)])
 def test_rhs_stage(Solver, N, p, stage, sub):
     eps, mu, sig, src = random_setup(N, p, seed=N * 10 + p)
@@ -121,7 +121,7 @@ def _solve_stage(Solver, N, p, stage, sub):
 
 
 @pytest.mark.parametrize("N,p,steps", [(1, 1, 3), (2, 3, 3), (3, 2, 4), (6, 2, 3), (5, 3, 3),
-                                       (37, 3, 2), (47, 2, 2)])
+                                       (37, 3, 2), (47, 2, 2), (4, 4, 2), (45, 4, 1)])
 def test_full_steps_random_material(Solver, N, p, steps):
     eps, mu, sig, src = random_setup(N, p, seed=100 + N)
     dt = 0.5 / N
@@ -155,6 +155,34 @@ def test_large_rounds_two_launches(Solver, precision, tol):
     E, H, t = prob.run(E, H, t, 1)
     got, _ = s.get_fields()
     compare_state(got, E, H, tol, ("n148", precision))
+
+
+@pytest.mark.parametrize("N,p", [(4, 3), (4, 4), (45, 4)])
+def test_full_steps_fp32_refine_random_material(Solver, N, p):
+    """FP32 mode (float32 bulk, float64 right-hand sides and one float64
+    correction of the E solve) on random per-DOF material from a random
+    (rough) state, two steps against the oracle.
+
+    Tolerance from the arithmetic: a step applies three float32 1D solves
+    per field (the H solve without correction), each with a relative error
+    of about kappa(M_1D) * 2^-24 at most, and a rough state excites the
+    worst-conditioned modes; so 2 * steps * 3 * kappa(M_1D) * 2^-24, kappa
+    from the oracle's 1D mass matrix (27 at p = 3, 69-82 at p = 4: 2e-5 and
+    5e-5 for two steps; measured at p = 4, N = 4: 3.9e-5)."""
+    steps = 2
+    kappa = np.linalg.cond(gram.gram_matrices(N, p)[0])
+    tol = 2 * steps * 3 * kappa * 2.0 ** -24
+    eps, mu, sig, src = random_setup(N, p, seed=200 + N)
+    dt = 0.5 / N
+    prob = maxwell.Problem(N, p, eps, mu, sig, dt, src)
+    s = make_gpu(Solver, N, p, eps, mu, sig, dt, src, "fp32_refine")
+    E, H = constrained_random_state(prob, 21)
+    s.set_fields(np.stack(E + H), 0.01)
+    s.step(steps)
+    E, H, t = prob.run(E, H, 0.01, steps)
+    got, _ = s.get_fields()
+    errs = compare_state(got, E, H, tol, ("fp32", N, p, tol))
+    print("fp32 random material", N, p, "tol", tol, "errors", errs)
 
 
 def test_mms16_manufactured_solution(Solver):
