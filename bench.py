@@ -187,7 +187,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path has no "
-              "multi-GPU implementation in this build", file=sys.stderr)
+              "multi-GPU implementation (the step runs on one GPU)", file=sys.stderr)
         sys.exit(2)
 
     import workloads
