@@ -899,7 +899,32 @@ __device__ __forceinline__ void spike_body(const SweepArgs& a) {
   T* xt = gex + Q * 64 + seg * (8 * 65);
   const int l0 = blockIdx.x * 64;
   T y[MR];
-  if (XAX) {
+  if (XAX && sizeof(T) == 4 && MR <= 40) {
+    // short float32 segments: every chunk's loads in flight at once (rows
+    // clamped), then the chunks go through the tile one by one
+    T v[MR / 8][8];
+#pragma unroll
+    for (int c = 0; c < MR / 8; ++c)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int e = lane + 64 * j, ln = e >> 3, rr = e & 7;
+        v[c][j] = in[size_t(min(l0 + ln, nl - 1)) * n + b0 + min(8 * c + rr, m - 1)];
+      }
+#pragma unroll
+    for (int c = 0; c < MR / 8; ++c) {
+      if (8 * c < m) {  // uniform
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int e = lane + 64 * j;
+          xt[(e & 7) * 65 + (e >> 3)] = v[c][j];
+        }
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int rr = 0; rr < 8; ++rr) y[8 * c + rr] = xt[rr * 65 + lane];
+        __builtin_amdgcn_wave_barrier();
+      }
+    }
+  } else if (XAX) {
 #pragma unroll
     for (int c0 = 0; c0 < MR; c0 += 8) {
       if (c0 < m) {  // uniform
