@@ -899,9 +899,9 @@ __device__ __forceinline__ void spike_body(const SweepArgs& a) {
   T* xt = gex + Q * 64 + seg * (8 * 65);
   const int l0 = blockIdx.x * 64;
   T y[MR];
-  if (XAX && sizeof(T) == 4 && MR <= 40) {
-    // short float32 segments: every chunk's loads in flight at once (rows
-    // clamped), then the chunks go through the tile one by one
+  if (XAX && MR <= 40) {
+    // short segments: every chunk's loads in flight at once (rows clamped),
+    // then the chunks go through the tile one by one
     T v[MR / 8][8];
 #pragma unroll
     for (int c = 0; c < MR / 8; ++c)
