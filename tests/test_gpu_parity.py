@@ -273,6 +273,35 @@ def test_repeatable_bitwise(Solver):
     assert np.array_equal(outs[0], outs[1])
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refine"])
+def test_profiling_pass_equals_graph_steps(Solver, precision):
+    """The eager profiling pass (the per-kernel timings of bench.py) runs the
+    same kernels as the captured graph: the same state after the same steps,
+    bit for bit, and one record per launch of a step."""
+    N, p = 45, 3  # n = 48: partitioned shared-axis solves, mixed-axis rounds
+    eps, mu, sig, src = random_setup(N, p, seed=11)
+    dt = 0.5 / N
+    prob = maxwell.Problem(N, p, eps, mu, sig, dt, src)
+    E, H = constrained_random_state(prob, 2)
+    outs = []
+    for mode in ("graph", "profile"):
+        s = make_gpu(Solver, N, p, eps, mu, sig, dt, src, precision)
+        s.set_fields(np.stack(E + H), 0.0)
+        if mode == "graph":
+            s.step(3)
+        else:
+            s.profile(3)
+            launches = s.profile_read()
+        outs.append(s.get_fields())
+        s.close()
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert outs[0][1] == outs[1][1]
+    kinds = [L["kind"] for L in launches]
+    assert kinds.count("rhs_E") == 2 and kinds.count("rhs_H") == 2
+    assert kinds.count("residual64") == (2 if precision == "fp32_refine" else 0)
+    assert all(L["ms"] > 0 for L in launches)
+
+
 def test_resume_equals_uninterrupted(Solver):
     N, p = 5, 2
     eps, mu, sig, src = random_setup(N, p, seed=4)
