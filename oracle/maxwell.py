@@ -229,10 +229,20 @@ class Problem:
         X, Y, Z = (self.ops[o] for o in ops)
         return banded.apply3(u, X, Y, Z, self.p)
 
+    def source_time(self, sub: int, t: float) -> float:
+        """Time at which the source of substep ``sub`` starting at t is
+        evaluated: the midpoint of the half step (reading R5), t + dt/4 in
+        substep 1 and t + 3 dt/4 in substep 2."""
+        return t + (0.25 if sub == 1 else 0.75) * self.dt
+
     def source_rows(self, c: int, t: float) -> np.ndarray:
-        """(J(t), V_rst) for component c: a g(t) B_r(xs) B_s(ys) B_t(zs)."""
+        """(J(t), V_rst) for component c: a g(t) B_r(xs) B_s(ys) B_t(zs) for
+        the point dipole; a source object with its own ``rows`` method
+        (e.g. ``SeparableSource``) computes the rows itself."""
         out = np.zeros((self.n,) * 3)
         src = self.source
+        if src is not None and hasattr(src, "rows"):
+            return src.rows(self, c, t)
         if src is None or src.comp != c or src.amp == 0.0:
             return out
         bx = bspline.basis(self.knots, self.p, [src.xs[0]])[0]
@@ -274,7 +284,7 @@ class Problem:
     def substep(self, sub: int, E, H, t: float):
         """One substep (sub = 1: n -> n+1/2, sub = 2: n+1/2 -> n+1)."""
         fields = {"E1": E[0], "E2": E[1], "E3": E[2], "H1": H[0], "H2": H[1], "H3": H[2]}
-        t_mid = t + (0.25 if sub == 1 else 0.75) * self.dt
+        t_mid = self.source_time(sub, t)
         En = []
         for c in range(3):
             R = self.rhs_E(sub, fields, c, t_mid)
@@ -310,6 +320,31 @@ class Problem:
             e += float(np.sum(E[c] * self.eps * self.apply(E[c], "MMM")))
             e += float(np.sum(H[c] * self.mu * self.apply(H[c], "MMM")))
         return e
+
+
+@dataclasses.dataclass
+class SeparableSource:
+    """A distributed current J = j(t) fx(x) fy(y) fz(z) e_comp (not in the
+    paper; reading R5 fixes where J enters).  Its rows (J(t), V_rst) =
+    j(t) (fx, B_r)(fy, B_s)(fz, B_t) are integrated with q Gauss-Legendre
+    points per element (the profiles need not be polynomials)."""
+
+    comp: int
+    j: object          # callable j(t)
+    fx: object         # callables of one coordinate (vectorised)
+    fy: object
+    fz: object
+    q: int = 12
+
+    def rows(self, prob: "Problem", c: int, t: float) -> np.ndarray:
+        if c != self.comp:
+            return np.zeros((prob.n,) * 3)
+        x, w = bspline.gauss_points(prob.N, self.q)
+        V = bspline.basis(prob.knots, prob.p, x)          # (Q, n)
+        ix = (w * self.fx(x)) @ V
+        iy = (w * self.fy(x)) @ V
+        iz = (w * self.fz(x)) @ V
+        return float(self.j(t)) * np.einsum("k,j,i->kji", iz, iy, ix)
 
 
 def problem_from_voxels(N: int, p: int, material, dt: float, source=None,
