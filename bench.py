@@ -5,17 +5,20 @@ Metric: field DOF-updates per second = 6 n^3 * steps / wall time of the
 timed steps (both substeps of a step update every E and H coefficient once),
 on the 128^3-element p=3 workload: a 256^3 voxel map of nested ellipsoidal
 shells (air / skull-like / tissue-like, seed 3), a dipole source in air at
-(0.5, 0.5, 0.04), dt = 1/256.  The headline run is the float32 bulk path with
-float64 factors and one float64 residual correction per E solve; the float64
-path is measured beside it.  All inputs are resident in device memory
+(0.5, 0.5, 0.04), dt = 1/256.  The headline run is the float32 mode (float32
+state and sweeps, factors computed in float64, every stage solved in
+increment form from a float64 residual of the old state); the float64 path
+is measured beside it.  All inputs are resident in device memory
 before the timed region starts.
 
 Per-kernel durations come from HIP events recorded around every kernel
 launch on the library's stream, in a second timed pass that enqueues the
 same kernels without the graph (graph replays cannot be split by events).
-The roofline object reports the kernel class with the largest share of the
-step time: algorithmic bytes per launch / average launch duration against
-the 8 TB/s HBM peak.
+The roofline object reports the single kernel with the largest share of the
+step time: its algorithmic bytes per launch / its average launch duration
+against the 8 TB/s HBM peak.  step_frac_hbm is the step's algorithmic
+traffic (130 words per coefficient and step) over the step time, against
+the same peak; step_bytes also gives the bytes the launches as built move.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 """
@@ -25,7 +28,6 @@ import argparse
 import hashlib
 import json
 import os
-import resource
 import sys
 import time
 
@@ -41,44 +43,78 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(launch, D, wbytes, refine=False):
+def algorithmic_bytes(launch, D, wbytes):
     """Bytes a launch must move at minimum (each array read or written once).
 
-    rhs_E:  6 fields + alpha, beta, gamma read, 3 right-hand sides written
-            (refine mode: float32 fields, float64 coefficients, the float64
-            right-hand sides and their float32 copies written);
-    rhs_H:  9 fields (H, E old, E new) + delta read, 3 written;
-    residual64 (refine mode): float32 solution x, float64 right-hand sides b
-            and alpha read, float32 residuals b - P x written;
+    rhs_E:  float64 path: 6 fields + gamma, beta, alpha read, 3 right-hand
+            sides written; float32 mode: the same arrays in float32 (the
+            increments b - P E_old: 6 fields, gamma - 1, beta, alpha read,
+            3 increments written);
+    rhs_H:  float64 path: 9 fields (H, E old, E new) + delta read, 3 written;
+            float32 mode: the increments b - M H_old read E old, E new and
+            delta only (6 + 1 read, 3 written);
     sweeps: per component the right-hand side read and the solution written,
-            plus the per-row coefficient on a material-modified axis.
+            plus the per-row coefficient on a material-modified axis, plus the
+            old state read where the float32 mode adds it (nacc).
     """
     k = launch["kind"]
+    refine = wbytes == 4
     if k == "rhs_E":
-        return D * (6 * 4 + 3 * 8 + 3 * 8 + 3 * 4) if refine else 12 * D * wbytes
+        return 12 * D * wbytes
     if k == "rhs_H":
-        return 13 * D * wbytes
-    if k == "residual64":
-        return D * (3 * 4 + 3 * 8 + 8 + 3 * 4)
-    return D * wbytes * (2 * launch["ncomp"] + launch["nmod"])
+        return (10 if refine else 13) * D * wbytes
+    return D * wbytes * (2 * launch["ncomp"] + launch["nmod"] + launch.get("nacc", 0))
 
 
-def summarize(launches, D, wbytes, refine):
-    by = {}
+def kernel_key(launch, nth, n, p, precision):
+    """Name of the HIP kernel a profiled launch ran (as rocprofv3 reports it,
+    without namespace and arguments); nth = index among launches of its kind
+    in the step (right-hand sides: 0 = substep 1, 1 = substep 2)."""
+    k = launch["kind"]
+    T = "double" if precision == "fp64" else "float"
+    if k in ("rhs_E", "rhs_H"):
+        sub = nth
+        if precision == "fp64":
+            stage = (0, 1)[sub] if k == "rhs_E" else (2, 3)[sub]
+            return f"rhs_kernel<double, double, double, double, {p}, {stage}>"
+        stage = (8, 9)[sub] if k == "rhs_E" else (10, 11)[sub]
+        return f"rhs_kernel<float, double, float, float, {p}, {stage}>"
+    spike = 48 <= n <= 288 and launch["nmod"] == 0
+    MR = 40 if (n + 3) // 4 <= 40 else 72
+    mod = "true" if launch["nmod"] else "false"
+    if k == "sweep_xyz":
+        return f"spike_mixed_kernel<{T}, {p}, {MR}>" if spike else \
+            f"sweep_mixed_kernel<{T}, {p}, {mod}>"
+    xax = "true" if k == "sweep_x" else "false"
+    return f"spike_kernel<{T}, {p}, {xax}, {MR}>" if spike else \
+        f"sweep_kernel<{T}, {p}, {xax}, {mod}>"
+
+
+def summarize(launches, D, n, p, precision):
+    """Per kernel: launches per step, total and mean duration, algorithmic bytes."""
+    wbytes = 8 if precision == "fp64" else 4
+    by, seen = {}, {}
     for L in launches:
-        b = by.setdefault(L["kind"], dict(total_ms=0.0, launches=0, bytes=0.0))
+        nth = seen.get(L["kind"], 0)
+        seen[L["kind"]] = nth + 1
+        key = kernel_key(L, nth, n, p, precision)
+        b = by.setdefault(key, dict(total_ms=0.0, launches=0, bytes=0.0, factor_bytes=0.0))
         b["total_ms"] += L["ms"]
         b["launches"] += 1
-        b["bytes"] += algorithmic_bytes(L, D, wbytes, refine)
-    for k, b in by.items():
+        b["bytes"] += algorithmic_bytes(L, D, wbytes)
+        # cached per-line factors ((2p+1) words per row: L, D*U, D) that the
+        # material-modified launches stream; in the counter traffic, not in
+        # the algorithmic bytes
+        b["factor_bytes"] += L["nmod"] * (2 * p + 1) * D * wbytes
+    for b in by.values():
         b["avg_ms"] = b["total_ms"] / b["launches"]
         b["achieved_GBs"] = b["bytes"] / (b["total_ms"] * 1e-3) / 1e9
     return by
 
 
-def traffic_from_profiles(kind, precision):
-    """HBM bytes per launch from committed rocprofv3 counter summaries, if they
-    were taken on the current kernel source; else None."""
+def traffic_from_profiles(key, precision):
+    """HBM bytes per launch of a kernel from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source; else None."""
     path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
     if not os.path.exists(path):
         return None
@@ -88,7 +124,13 @@ def traffic_from_profiles(kind, precision):
     digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
     if rec.get("kernels_sha256") != digest:
         return None
-    return rec.get("per_launch_bytes", {}).get(f"{precision}:{kind}")
+    return rec.get("per_launch_bytes", {}).get(f"{precision}:{key}")
+
+
+# Algorithmic words per step in units of D = n^3 (both substeps; each 1D
+# pass reads and writes its array once, the x sweep fused into the
+# right-hand side): E stage 38 and H stage 27 per substep.
+MODEL_WORDS_PER_STEP = 130
 
 
 def run_gpu(precision, w, steps, warmup):
@@ -112,68 +154,90 @@ def run_gpu(precision, w, steps, warmup):
     s.sync()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    # kernel durations: the same kernels enqueued eagerly on the same stream
-    # with HIP events around every launch, averaged over the profiled steps
+    # kernel durations: the same kernels enqueued eagerly on the library's
+    # stream with HIP events around every launch, averaged over the steps
     s.profile(max(5, min(steps, 50)))
     launches = s.profile_read()
     wbytes = 8 if precision == "fp64" else 4
-    refine = precision != "fp64"
-    kinds = summarize(launches, D, wbytes, refine)
+    kernels = summarize(launches, D, n, w.p, precision)
     EH, t = s.get_fields()
     finite = bool(np.isfinite(EH).all())
     s.close()
     ms_step = elapsed * 1e3 / steps
     value = 6.0 * D * steps / elapsed
-    dom = max(kinds, key=lambda k: kinds[k]["total_ms"])
-    b = kinds[dom]
-    per_launch_bytes = b["bytes"] / b["launches"]
-    achieved = per_launch_bytes / (b["avg_ms"] * 1e-3) / 1e9
-    # per-line factors streamed by the class's material-modified launches
-    # ((2p+1) words per row: L, D*U, D): in the counter traffic, not in the
-    # algorithmic bytes
-    dom_launches = [L for L in launches if L["kind"] == dom]
-    factor_bytes = sum(L["nmod"] * (2 * w.p + 1) * D * wbytes for L in dom_launches)
+    # the single kernel with the largest share of the step time
+    dom = max(kernels, key=lambda k: kernels[k]["total_ms"])
+    b = kernels[dom]
+    per_launch = b["bytes"] / b["launches"]
+    achieved = per_launch / (b["avg_ms"] * 1e-3) / 1e9
     roofline = {
         "bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
         "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
         "traffic": traffic_from_profiles(dom, precision),
-        "bytes_per_launch": int(per_launch_bytes), "avg_launch_ms": round(b["avg_ms"], 5),
-        "factor_bytes_per_launch": int(factor_bytes / max(1, len(dom_launches))),
+        "bytes_per_launch": int(per_launch), "avg_launch_ms": round(b["avg_ms"], 5),
+        "launches_per_step": b["launches"],
+        "share_of_step": round(b["total_ms"] / sum(k["total_ms"] for k in kernels.values()), 4),
+        "factor_bytes_per_launch": int(b["factor_bytes"] / b["launches"]),
     }
-    step_bytes = sum(algorithmic_bytes(L, D, wbytes, refine) for L in launches)
-    kernel_ms = sum(L["ms"] for L in launches)
+    model_bytes = MODEL_WORDS_PER_STEP * D * wbytes
+    executed_bytes = sum(k["bytes"] for k in kernels.values())
     return dict(value=value, ms_per_step=ms_step, roofline=roofline, finite=finite,
                 kernels={k: {kk: (round(vv, 5) if isinstance(vv, float) else vv)
-                             for kk, vv in v.items()} for k, v in kinds.items()},
-                step_algorithmic_bytes=int(step_bytes),
-                step_kernel_ms=round(kernel_ms, 4),
-                step_frac_hbm=round(step_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4))
+                             for kk, vv in v.items()} for k, v in kernels.items()},
+                step_kernel_ms=round(sum(L["ms"] for L in launches), 4),
+                step_bytes={"model_130_words": int(model_bytes), "executed": int(executed_bytes),
+                            "overhead": int(executed_bytes - model_bytes)},
+                step_frac_hbm=round(model_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4))
 
 
-def cpu_baseline(w):
-    """The float64 oracle on the host: one full step of the same workload."""
+def _oracle_steps(args):
+    """Worker: whole oracle steps of a workload until about `budget` seconds."""
+    name, budget, seed = args
+    import workloads
     from oracle import maxwell
 
+    w = workloads.make(name)
     n = w.N + w.p
     prob = maxwell.problem_from_voxels(w.N, w.p, w.material, w.dt, w.source)
-    rng = np.random.default_rng(0)
+    rng = np.random.default_rng(seed)
     E = [1e-3 * rng.standard_normal((n, n, n)) for _ in range(3)]
     H = [1e-3 * rng.standard_normal((n, n, n)) for _ in range(3)]
     E, H = prob.constrain(E, H)
-    r0 = resource.getrusage(resource.RUSAGE_SELF)
     t0 = time.perf_counter()
     steps, t = 0, 0.45
-    # whole steps until about 10 s of work (at most 8 steps)
-    while steps < 8 and (steps == 0 or time.perf_counter() - t0 < 10.0):
+    while steps < 8 and (steps == 0 or time.perf_counter() - t0 < budget):
         E, H, t = prob.step(E, H, t)
         steps += 1
-    wall = time.perf_counter() - t0
-    r1 = resource.getrusage(resource.RUSAGE_SELF)
-    cpu = (r1.ru_utime - r0.ru_utime) + (r1.ru_stime - r0.ru_stime)
-    return {"value": 6.0 * n ** 3 * steps / wall, "unit": "field DOF-updates/s",
-            "cores": max(1, int(round(cpu / wall))), "kind": "oracle",
-            "sample": f"{steps} full step(s) (both substeps) of the {w.N}^3 p={w.p} workload, "
-                      f"float64 NumPy oracle, {wall:.1f} s wall, {cpu:.1f} s CPU"}
+    return steps, time.perf_counter() - t0, t0
+
+
+def cpu_baseline(name, n):
+    """The float64 oracle on the host, on one core and on all usable cores.
+
+    The oracle is NumPy with one thread per process; the all-cores figure
+    runs one independent oracle per core (each stepping its own state of the
+    same workload) and counts the DOF-updates of all of them over the wall
+    time from the first start to the last end."""
+    import concurrent.futures
+    import multiprocessing as mp
+
+    one_steps, one_wall, _ = _oracle_steps((name, 10.0, 0))
+    single = 6.0 * n ** 3 * one_steps / one_wall
+    ncpu = os.cpu_count() or 1
+    cores = max(1, min(ncpu, 16))
+    ctx = mp.get_context("spawn")
+    with concurrent.futures.ProcessPoolExecutor(cores, mp_context=ctx) as ex:
+        res = list(ex.map(_oracle_steps, [(name, 10.0, k + 1) for k in range(cores)]))
+    start = min(r[2] for r in res)
+    end = max(r[2] + r[1] for r in res)
+    total_steps = sum(r[0] for r in res)
+    value = 6.0 * n ** 3 * total_steps / (end - start)
+    return {"value": value, "unit": "field DOF-updates/s", "cores": cores, "kind": "oracle",
+            "sample": f"{cores} concurrent float64 NumPy oracles (one per core, one thread "
+                      f"each, host has {ncpu} logical CPUs), {total_steps} full steps of the "
+                      f"{name} workload in {end - start:.1f} s wall",
+            "single_core": {"value": single, "cores": 1,
+                            "sample": f"{one_steps} full step(s), {one_wall:.1f} s wall"}}
 
 
 def main():
@@ -194,6 +258,12 @@ def main():
 
     w = workloads.make("shell128")
     n = w.N + w.p
+    cpu = None
+    if not args.no_cpu_baseline:
+        # before the GPU is touched: the worker processes start clean
+        cpu = cpu_baseline("shell128", n)
+        log(f"cpu oracle: {cpu['value']:.3e} DOF/s on {cpu['cores']} core(s), "
+            f"{cpu['single_core']['value']:.3e} on one")
     log(f"workload shell128: N={w.N} p={w.p} n={n} dt={w.dt}")
     res32 = run_gpu("fp32_refine", w, args.steps, args.warmup)
     log(f"fp32_refine: {res32['ms_per_step']:.3f} ms/step {res32['value']:.3e} DOF/s")
@@ -210,11 +280,7 @@ def main():
             log(f"shell256 {prec}: {r['ms_per_step']:.3f} ms/step {r['value']:.3e} DOF/s")
             big[prec] = {"value": r["value"], "ms_per_step": r["ms_per_step"],
                          "roofline": r["roofline"], "step_frac_hbm": r["step_frac_hbm"],
-                         "finite": r["finite"]}
-    cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline(w)
-        log(f"cpu oracle: {cpu['value']:.3e} DOF/s on {cpu['cores']} core(s)")
+                         "step_bytes": r["step_bytes"], "finite": r["finite"]}
 
     out = {
         "metric": "field DOF-updates/s per ADI step at 128^3 p=3 (FP64/FP32); % HBM roofline",
@@ -231,18 +297,20 @@ def main():
         "data": "synthetic",
         "config": {"workload": "shell128: 128^3 elements, p=3, n=131 coefficients per axis, "
                                "256^3 ellipsoidal-shell voxel map (seed 3), dipole in air at "
-                               "(0.5,0.5,0.04), dt=1/256, float32 bulk + float64 factors + one "
-                               "float64 residual correction per E solve",
+                               "(0.5,0.5,0.04), dt=1/256, float32 state and sweeps, factors "
+                               "computed in float64, every stage solved in increment form "
+                               "from a float64 residual of the old state",
                    "N": w.N, "p": w.p, "dofs": 6 * n ** 3},
         "roofline": res32["roofline"],
         "cpu_baseline": cpu,
+        "step_frac_hbm": res32["step_frac_hbm"],
+        "step_bytes": res32["step_bytes"],
+        "kernels": res32["kernels"],
         "fp64": {"value": res64["value"], "ms_per_step": res64["ms_per_step"], "dtype": "f64",
                  "roofline": res64["roofline"], "step_frac_hbm": res64["step_frac_hbm"],
-                 "kernels": res64["kernels"], "finite": res64["finite"]},
-        "fp32_refine_detail": {"kernels": res32["kernels"],
-                               "step_frac_hbm": res32["step_frac_hbm"],
-                               "step_algorithmic_bytes": res32["step_algorithmic_bytes"],
-                               "finite": res32["finite"]},
+                 "step_bytes": res64["step_bytes"], "kernels": res64["kernels"],
+                 "finite": res64["finite"]},
+        "finite": res32["finite"],
         "shell256": big,
     }
     print(json.dumps(out), flush=True)

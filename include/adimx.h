@@ -48,8 +48,12 @@ enum {
 
 enum {
   ADI_FP64 = 0,        /* fields, right-hand sides and sweeps in float64     */
-  ADI_FP32_REFINE = 1  /* float32 bulk, float64 factors, one float64 residual
-                          correction per E solve                              */
+  ADI_FP32_REFINE = 1  /* float32 state and sweeps, factors computed in
+                          float64; every stage solved in increment form: its
+                          right-hand-side kernel forms the residual of the old
+                          state, b - P x_old, in float64 arithmetic, the
+                          float32 sweeps solve P d = b - P x_old and the last
+                          sweep stores x_old + d                               */
 };
 
 enum {
@@ -154,16 +158,17 @@ int adi_sync(adi_ctx* ctx);
  * around every kernel launch, waits after each step and accumulates every
  * launch's duration (the state advances by nsteps steps).  adi_profile_read
  * reports, for each launch of a step in launch order: its kind (0 = E
- * right-hand side, 1 = H right-hand side, 2 = float64 residual, 3 = x-line
- * solves, 4 = y/z-line solves, 5 = x- and y/z-line solves of one round in
- * one launch), the number of field components it processes,
- * how many of those use per-line (material-modified) factors, and its mean
- * duration in milliseconds.  *nout receives the number of launches per step
+ * right-hand side, 1 = H right-hand side, 3 = x-line solves, 4 = y/z-line
+ * solves, 5 = x- and y/z-line solves of one round in one launch), the
+ * number of field components it processes, how many of those use per-line
+ * (material-modified) factors, how many add the old state to their solution
+ * (the last solves of the float32 mode), and its mean duration in
+ * milliseconds.  *nout receives the number of launches per step
  * (the arrays hold cap entries).
  */
 int adi_profile_run(adi_ctx* ctx, int nsteps);
 int adi_profile_read(adi_ctx* ctx, int cap, int* nout, int* kind, int* ndesc, int* nmod,
-                     float* ms);
+                     int* nacc, float* ms);
 
 const char* adi_last_error(const adi_ctx* ctx);
 void adi_destroy(adi_ctx* ctx);
@@ -182,6 +187,22 @@ void adi_destroy(adi_ctx* ctx);
  */
 int adi_mms_project(adi_ctx* ctx, int q, double t);
 int adi_mms_errors(adi_ctx* ctx, int q, double* out);
+
+/*
+ * L2 projection of a state given by its values at Gauss points (section
+ * "Numerical code verification with manufactured solution": the initial
+ * state is a projection of the given fields onto the spline space; the
+ * problem statement of section "Alternating directions splitting for Maxwell
+ * equations" takes E and H at t = 0 as data).  vals_qp holds 6 (N q)^3
+ * float64 values, [component E1..E3,H1..H3][z][y][x], on the tensor grid of
+ * the q-point Gauss-Legendre rule of every element (point e q + g of an axis
+ * is Gauss point g of element e, x fastest); 1 <= q <= 16.  The state
+ * becomes, per component, the solution of (M (x) M (x) M) c = (f, B_r B_s B_t)
+ * with the PEC-constrained coefficients zero, and the time t.  Copied before
+ * the call returns.  ENONFINITE for a value that is not finite, ESTATE before
+ * adi_factor.  Waits for the context's stream and for the projection.
+ */
+int adi_project(adi_ctx* ctx, const double* vals_qp, int q, double t);
 
 /*
  * Single hot-path stages on host buffers (float64 in and out), for testing

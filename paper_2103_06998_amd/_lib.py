@@ -46,9 +46,10 @@ SIGNATURES = {
     "adi_solve": (_I, [_P, _I, _I, _D]),
     "adi_mms_project": (_I, [_P, _I, ctypes.c_double]),
     "adi_mms_errors": (_I, [_P, _I, _D]),
+    "adi_project": (_I, [_P, _D, _I, ctypes.c_double]),
     "adi_profile_run": (_I, [_P, _I]),
     "adi_profile_read": (_I, [_P, _I, ctypes.POINTER(_I), ctypes.POINTER(_I),
-                              ctypes.POINTER(_I), ctypes.POINTER(_I),
+                              ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_I),
                               ctypes.POINTER(ctypes.c_float)]),
     # learned closure
     "adi_nn_create": (_I, [ctypes.POINTER(_P), _I, _I, _I, _P]),

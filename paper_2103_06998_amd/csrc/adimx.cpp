@@ -8,8 +8,11 @@
 //            (that order solves the row-scaled system of eq. dupa1ab
 //            exactly; the remaining two axes have shared factors);
 //   H stage: right-hand sides of H1, H2, H3, then mass solves along x, y, z.
-// In ADI_FP32_REFINE mode the E stage is followed by a float64 residual of
-// the float32 solve and one correction solve.
+// In ADI_FP32_REFINE mode every stage is solved in increment form: the
+// right-hand-side kernel forms b - P x_old in float64 arithmetic from the
+// float32 state (the residual of the old state), the float32 sweeps solve
+// P d = b - P x_old, and the last sweep adds x_old, so the float32 solve's
+// rounding scales with the increment d instead of with the state.
 #include "adimx.h"
 #include "adimx_internal.h"
 #include "closure_internal.h"
@@ -69,6 +72,7 @@ struct adi_ctx {
   void* B[4] = {};          // 4 field buffers of 3 D elements; B0|B1 = state (E|H)
   void* coefT[4] = {};      // alpha, beta, gamma, delta in the field type
   double* coef64[4] = {};   // float64 copies (refine mode), else alias of coefT
+  void* gm1T = nullptr;     // gamma - 1 (refine mode: group coefficient of the E increments)
   void* bandT = nullptr;    // [M,A,B,S][n][2p+1] in the field type
   double* band64 = nullptr; // same in float64
   void* zwT = nullptr;      // z weights [M,A,B,S][k][2p+1] in the field type
@@ -80,8 +84,6 @@ struct adi_ctx {
   void* mL[6] = {}, *mU[6] = {}, *mD[6] = {};     // per-line factors, system (s-1)*3 + c
   double* minratio = nullptr;
   double* d_t = nullptr;
-  float* R32 = nullptr;     // residual scratch (refine mode), 3 D
-  double* b64 = nullptr;    // float64 E right-hand sides (refine mode), 3 D
 
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -90,7 +92,7 @@ struct adi_ctx {
   // kernel of a step, durations summed over the profiled steps
   bool profiling = false;
   std::vector<hipEvent_t> events;      // 2 per launch
-  std::vector<int> launch_kind, launch_ndesc, launch_nmod;
+  std::vector<int> launch_kind, launch_ndesc, launch_nmod, launch_nacc;
   std::vector<double> launch_ms_sum;
   int profiled_steps = 0;
   size_t launch_idx = 0;
@@ -144,6 +146,7 @@ size_t layout(adi_ctx* c, unsigned char* base) {
   for (int i = 0; i < 4; ++i)
     c->coef64[i] = c->refine() ? reinterpret_cast<double*>(take(D * 8))
                                : reinterpret_cast<double*>(c->coefT[i]);
+  c->gm1T = c->refine() ? take(D * es) : nullptr;
   c->bandT = take(size_t(4) * n * W * es);
   c->band64 = reinterpret_cast<double*>(take(size_t(4) * n * W * 8));
   c->zwT = take(size_t(4) * n * W * es);
@@ -167,8 +170,6 @@ size_t layout(adi_ctx* c, unsigned char* base) {
   }
   c->minratio = reinterpret_cast<double*>(take(size_t(n) * n * 8));
   c->d_t = reinterpret_cast<double*>(take(8));
-  c->R32 = c->refine() ? reinterpret_cast<float*>(take(3 * D * 4)) : nullptr;
-  c->b64 = c->refine() ? reinterpret_cast<double*>(take(3 * D * 8)) : nullptr;
   return cur + 256;
 }
 
@@ -220,7 +221,8 @@ enum LaunchKind { kKindRhsE = 0, kKindRhsH = 1, kKindResidual = 2, kKindSweepX =
 
 // Run `launch` on stream s; when profiling, bracket it with two events.
 template <typename F>
-hipError_t timed(adi_ctx* c, hipStream_t s, int kind, int ndesc, int nmod, F&& launch) {
+hipError_t timed(adi_ctx* c, hipStream_t s, int kind, int ndesc, int nmod, int nacc,
+                 F&& launch) {
   if (!c->profiling) return launch();
   const size_t i = c->launch_idx++;
   while (c->events.size() < 2 * (i + 1)) {
@@ -233,10 +235,12 @@ hipError_t timed(adi_ctx* c, hipStream_t s, int kind, int ndesc, int nmod, F&& l
     c->launch_kind.resize(i + 1);
     c->launch_ndesc.resize(i + 1);
     c->launch_nmod.resize(i + 1);
+    c->launch_nacc.resize(i + 1);
   }
   c->launch_kind[i] = kind;
   c->launch_ndesc[i] = ndesc;
   c->launch_nmod[i] = nmod;
+  c->launch_nacc[i] = nacc;
   hipError_t e = hipEventRecord(c->events[2 * i], s);
   if (e != hipSuccess) return e;
   e = launch();
@@ -251,11 +255,11 @@ RhsArgs<T> rhs_args(adi_ctx* c, const void* const* f, int nf, void* const* out, 
   for (int i = 0; i < nf; ++i) a.f[i] = f[i];
   for (int i = 0; i < 3; ++i) a.out[i] = out[i];
   if (kindH) {
-    a.coef[0] = static_cast<const T*>(c->coefT[3]);
+    a.coef[0] = c->coefT[3];  // delta
   } else {
-    a.coef[0] = static_cast<const T*>(c->coefT[2]);  // gamma
-    a.coef[1] = static_cast<const T*>(c->coefT[1]);  // beta
-    a.coef[2] = static_cast<const T*>(c->coefT[0]);  // alpha
+    a.coef[0] = c->coefT[2];  // gamma
+    a.coef[1] = c->coefT[1];  // beta
+    a.coef[2] = c->coefT[0];  // alpha
   }
   a.band = static_cast<const T*>(c->bandT);
   a.zw = static_cast<const T*>(c->zwT);
@@ -317,13 +321,14 @@ hipError_t next_event(adi_ctx* c, hipEvent_t* e) {
 }
 
 // Enqueue the three rounds of 1D solves of one stage on the three components
-// of `buf` (in place).  If `final_out` is given, the last solve of each
-// component writes final_out + solution instead (refine-mode correction).
+// of `buf` (in place).  If `acc_base` is given, the last solve of each
+// component adds the matching component of acc_base to its solution (the
+// increment form of the float32 mode: x_new = x_old + d).
 // Within a round the x-line launch and the y/z-line launch touch different
 // components: outside the profiling pass the x launch runs on a second
 // branch (the side stream, forked from and joined back into s).
 template <typename T>
-hipError_t enqueue_solves(adi_ctx* c, int kindH, int sub, void* buf, void* final_out,
+hipError_t enqueue_solves(adi_ctx* c, int kindH, int sub, void* buf, const void* acc_base,
                           hipStream_t s) {
   int order[3][3];
   for (int ci = 0; ci < 3; ++ci) axis_order(kindH, sub, ci, order[ci]);
@@ -336,13 +341,9 @@ hipError_t enqueue_solves(adi_ctx* c, int kindH, int sub, void* buf, void* final
         const int ax = order[ci][r];
         if ((ax == 0) != (xgroup == 1)) continue;
         void* in = comp(buf, ci, c);
-        void* out = in;
-        const void* acc = nullptr;
-        if (final_out && r == 2) {
-          out = comp(final_out, ci, c);
-          acc = out;
-        }
-        a.d[nd[xgroup]++] = desc_for(c, kindH, sub, ci, ax, in, out, acc);
+        const void* acc =
+            (acc_base && r == 2) ? comp(const_cast<void*>(acc_base), ci, c) : nullptr;
+        a.d[nd[xgroup]++] = desc_for(c, kindH, sub, ci, ax, in, in, acc);
       }
       a.n = c->n;
       a.nlines = c->n * c->n;
@@ -366,7 +367,8 @@ hipError_t enqueue_solves(adi_ctx* c, int kindH, int sub, void* buf, void* final
         for (int q = 0; q < nd[0]; ++q) a.d[nd[1] + q] = grp[0].d[q];
         a.xaxis = 2;
         a.spike = (c->spike_ok && mall == 0) ? 1 : 0;
-        hipError_t e = timed(c, s, kKindSweepXYZ, nall, mall,
+        const int nacc = (acc_base && r == 2) ? nall : 0;
+        hipError_t e = timed(c, s, kKindSweepXYZ, nall, mall, nacc,
                              [&] { return launch_sweep<T>(c->p, nall, a, s); });
         if (e != hipSuccess) return e;
         continue;
@@ -386,7 +388,8 @@ hipError_t enqueue_solves(adi_ctx* c, int kindH, int sub, void* buf, void* final
       int nmod = 0;
       for (int q = 0; q < nd[xgroup]; ++q) nmod += a.d[q].modified;
       hipStream_t ls = (branch && xgroup == 1) ? c->side : s;
-      hipError_t e = timed(c, ls, xgroup ? kKindSweepX : kKindSweepYZ, nd[xgroup], nmod,
+      const int nacc = (acc_base && r == 2) ? nd[xgroup] : 0;
+      hipError_t e = timed(c, ls, xgroup ? kKindSweepX : kKindSweepYZ, nd[xgroup], nmod, nacc,
                            [&] { return launch_sweep<T>(c->p, nd[xgroup], a, ls); });
       if (e != hipSuccess) return e;
     }
@@ -409,7 +412,8 @@ hipError_t enqueue_step_t(adi_ctx* c, hipStream_t s) {
     void* Hin = sub == 1 ? B[1] : B[3];
     void* Eout = sub == 1 ? B[2] : B[0];
     void* Hout = sub == 1 ? B[3] : B[1];
-    // E stage
+    // E stage: right-hand sides (float32 mode: increments b - P E_old) into
+    // Eout, then the three solves in place (float32 mode: + E_old)
     {
       const void* f[6] = {comp(Ein, 0, c), comp(Ein, 1, c), comp(Ein, 2, c),
                           comp(Hin, 0, c), comp(Hin, 1, c), comp(Hin, 2, c)};
@@ -417,51 +421,21 @@ hipError_t enqueue_step_t(adi_ctx* c, hipStream_t s) {
       hipError_t e;
       if (!c->refine()) {
         RhsArgs<T> a = rhs_args<T>(c, f, 6, out, 0, sub);
-        e = timed(c, s, kKindRhsE, 3, 0, [&] {
+        e = timed(c, s, kKindRhsE, 3, 0, 0, [&] {
           return launch_rhs<T>(sub == 1 ? kStageE1 : kStageE2, c->p, a, s);
         });
-        if (e != hipSuccess) return e;
-        e = enqueue_solves<T>(c, 0, sub, Eout, nullptr, s);
-        if (e != hipSuccess) return e;
       } else {
-        // float64 right-hand sides b (kept for the residual) and their
-        // float32 copies for the float32 solve
         RhsArgs<double> a = rhs_args<double>(c, f, 6, out, 0, sub);
-        for (int i = 0; i < 3; ++i) {
-          a.out[i] = c->b64 + size_t(i) * c->D;
-          a.out2[i] = out[i];
-        }
-        a.coef[0] = c->coef64[2];
-        a.coef[1] = c->coef64[1];
-        a.coef[2] = c->coef64[0];
+        a.coef[0] = c->gm1T;  // gamma - 1: the mass part of P E folded in
         a.band = c->band64;
         a.zw = c->zw64;
-        e = timed(c, s, kKindRhsE, 3, 0, [&] {
-          return launch_rhs_e64(sub == 1 ? kStageE1 : kStageE2, c->p, a, s);
+        e = timed(c, s, kKindRhsE, 3, 0, 0, [&] {
+          return launch_rhs_inc(sub == 1 ? kStageEd1 : kStageEd2, c->p, a, s);
         });
-        if (e != hipSuccess) return e;
-        e = enqueue_solves<float>(c, 0, sub, Eout, nullptr, s);
-        if (e != hipSuccess) return e;
-        // residual r = b - P x in float64 (stored float32), one correction solve
-        RhsArgs<double> r{};
-        for (int i = 0; i < 3; ++i) {
-          r.f[i] = comp(Eout, i, c);
-          r.bin[i] = c->b64 + size_t(i) * c->D;
-          r.out[i] = c->R32 + size_t(i) * c->D;
-        }
-        r.coef[2] = c->coef64[0];  // alpha
-        r.band = c->band64;
-        r.zw = c->zw64;
-        r.n = c->n;
-        r.zchunk = pick_zchunk(c->n);
-        r.tnow = c->d_t;
-        e = timed(c, s, kKindResidual, 3, 0, [&] {
-          return launch_residual(sub == 1 ? kStageQ1 : kStageQ2, c->p, r, s);
-        });
-        if (e != hipSuccess) return e;
-        e = enqueue_solves<float>(c, 0, sub, c->R32, Eout, s);
-        if (e != hipSuccess) return e;
       }
+      if (e != hipSuccess) return e;
+      e = enqueue_solves<T>(c, 0, sub, Eout, c->refine() ? Ein : nullptr, s);
+      if (e != hipSuccess) return e;
     }
     // H stage
     {
@@ -472,27 +446,27 @@ hipError_t enqueue_step_t(adi_ctx* c, hipStream_t s) {
       hipError_t e;
       if (!c->refine()) {
         RhsArgs<T> a = rhs_args<T>(c, f, 9, out, 1, sub);
-        e = timed(c, s, kKindRhsH, 3, 0, [&] {
+        e = timed(c, s, kKindRhsH, 3, 0, 0, [&] {
           return launch_rhs<T>(sub == 1 ? kStageH1 : kStageH2, c->p, a, s);
         });
       } else {
-        // float64 arithmetic on the float32 fields keeps the H right-hand
-        // side's cancellations out of float32 (H has no correction solve)
+        // increments b - M H_old: the delta terms alone (H_old is not read)
         RhsArgs<double> a = rhs_args<double>(c, f, 9, out, 1, sub);
-        a.coef[0] = c->coef64[3];
         a.band = c->band64;
         a.zw = c->zw64;
-        e = timed(c, s, kKindRhsH, 3, 0, [&] {
-          return launch_rhs_e64(sub == 1 ? kStageH1 : kStageH2, c->p, a, s);
+        e = timed(c, s, kKindRhsH, 3, 0, 0, [&] {
+          return launch_rhs_inc(sub == 1 ? kStageHd1 : kStageHd2, c->p, a, s);
         });
       }
       if (e != hipSuccess) return e;
       // H: x, y, z (all shared factors); the last launch advances the time
+      // and, in the float32 mode, adds H_old
       for (int ax = 0; ax < 3; ++ax) {
         SweepArgs w{};
+        const bool add = c->refine() && ax == 2;
         for (int ci = 0; ci < 3; ++ci) {
           void* io = comp(Hout, ci, c);
-          w.d[ci] = desc_for(c, 1, sub, ci, ax, io, io, nullptr);
+          w.d[ci] = desc_for(c, 1, sub, ci, ax, io, io, add ? comp(Hin, ci, c) : nullptr);
         }
         w.n = c->n;
         w.nlines = c->n * c->n;
@@ -502,7 +476,7 @@ hipError_t enqueue_step_t(adi_ctx* c, hipStream_t s) {
           w.tick_t = c->d_t;
           w.tick_dt = c->dt;
         }
-        e = timed(c, s, ax == 0 ? kKindSweepX : kKindSweepYZ, 3, 0,
+        e = timed(c, s, ax == 0 ? kKindSweepX : kKindSweepYZ, 3, 0, add ? 3 : 0,
                   [&] { return launch_sweep<T>(c->p, 3, w, s); });
         if (e != hipSuccess) return e;
       }
@@ -839,7 +813,7 @@ int adi_factor(adi_ctx* c, double dt) {
   // trapezoidal conductivity term: c = sigma dt / (4 eps),
   // alpha = dt^2/(4 eps mu (1+c)), beta = dt/(2 eps (1+c)),
   // gamma = (1-c)/(1+c), delta = dt/(2 mu)
-  std::vector<double> co[4];
+  std::vector<double> co[5];
   for (auto& v : co) v.resize(D);
   // (a local time step per test function replaces dt in its row)
   for (size_t i = 0; i < D; ++i) {
@@ -850,12 +824,14 @@ int adi_factor(adi_ctx* c, double dt) {
     co[1][i] = tt / (2.0 * e * (1.0 + cc));
     co[2][i] = (1.0 - cc) / (1.0 + cc);
     co[3][i] = tt / (2.0 * m);
+    co[4][i] = -2.0 * cc / (1.0 + cc);  // gamma - 1 without cancellation
   }
   for (int i = 0; i < 4; ++i) {
     if ((st = upload(c, c->coefT[i], co[i])) != ADI_OK) return st;
     if (c->refine())
       HIPCHK(c, hipMemcpy(c->coef64[i], co[i].data(), D * 8, hipMemcpyHostToDevice));
   }
+  if (c->refine() && (st = upload(c, c->gm1T, co[4])) != ADI_OK) return st;
 
   // per-line factors of the modified systems (always Dirichlet: the modified
   // axis of E_c is never axis c)
@@ -999,7 +975,7 @@ int adi_profile_run(adi_ctx* c, int nsteps) {
 }
 
 int adi_profile_read(adi_ctx* c, int cap, int* nout, int* kind, int* ndesc, int* nmod,
-                     float* ms) {
+                     int* nacc, float* ms) {
   if (!c || !nout) return ADI_EINVAL;
   if (c->profiled_steps == 0) return fail(c, ADI_ESTATE, "run adi_profile_run first");
   const int n = int(c->launch_ms_sum.size());
@@ -1008,6 +984,7 @@ int adi_profile_read(adi_ctx* c, int cap, int* nout, int* kind, int* ndesc, int*
     if (kind) kind[i] = c->launch_kind[i];
     if (ndesc) ndesc[i] = c->launch_ndesc[i];
     if (nmod) nmod[i] = c->launch_nmod[i];
+    if (nacc) nacc[i] = c->launch_nacc[i];
     if (ms) ms[i] = float(c->launch_ms_sum[i] / c->profiled_steps);
   }
   return ADI_OK;
@@ -1279,16 +1256,15 @@ int adi_closure_rejected(adi_ctx* c, int* count) {
 // ------------------------------------------------ manufactured solution
 namespace {
 
-// Gauss tables of the q-point rule on every element (one axis; the patch
-// is a cube) on the device, and the buffers of the projection and errors.
-int mms_ready(adi_ctx* c, int q) {
-  if (q < 1 || q > 16) return fail(c, ADI_EINVAL, "quadrature points per element must be 1..16");
-  if (c->mms_q == q) return ADI_OK;
-  const int N = c->N, p = c->p, Q = N * q;
+// Gauss tables of the q-point rule on every element of one axis (the patch
+// is a cube): coordinates x[Q], weights w[Q], then the p + 1 basis values
+// bv[Q][p+1] and derivatives bd[Q][p+1] of each point's element, Q = N q.
+void mms_host_tables(int N, int p, int q, std::vector<double>& tab) {
+  const int Q = N * q;
   std::vector<double> gx, gw;
   gauss_legendre(q, gx, gw);
   const std::vector<double> t = open_knots(N, p);
-  std::vector<double> tab(size_t(Q) * (2 + 2 * (p + 1)));
+  tab.assign(size_t(Q) * (2 + 2 * (p + 1)), 0.0);
   double* X = tab.data();
   double* Wt = X + Q;
   double* BV = Wt + Q;
@@ -1305,6 +1281,30 @@ int mms_ready(adi_ctx* c, int q) {
         BD[size_t(a) * (p + 1) + r] = d[r];
       }
     }
+}
+
+// The device tables of mms_host_tables at `base`.
+mms::Tables tables_at(const double* base, int N, int p, int q) {
+  const int Q = N * q;
+  mms::Tables tb{};
+  tb.x = base;
+  tb.w = base + Q;
+  tb.bv = base + 2 * Q;
+  tb.bd = base + 2 * Q + size_t(Q) * (p + 1);
+  tb.N = N;
+  tb.p = p;
+  tb.q = q;
+  return tb;
+}
+
+// Tables on the device, and the buffers of the projection and errors
+// (allocated on first use and whenever q changes).
+int mms_ready(adi_ctx* c, int q) {
+  if (q < 1 || q > 16) return fail(c, ADI_EINVAL, "quadrature points per element must be 1..16");
+  if (c->mms_q == q) return ADI_OK;
+  const int N = c->N, p = c->p, Q = N * q;
+  std::vector<double> tab;
+  mms_host_tables(N, p, q, tab);
   if (c->mms_tab) hipFree(c->mms_tab);
   if (c->mms_vals) hipFree(c->mms_vals);
   c->mms_tab = nullptr;
@@ -1313,22 +1313,24 @@ int mms_ready(adi_ctx* c, int q) {
   HIPCHK(c, hipMalloc(reinterpret_cast<void**>(&c->mms_tab), tab.size() * 8));
   HIPCHK(c, hipMemcpy(c->mms_tab, tab.data(), tab.size() * 8, hipMemcpyHostToDevice));
   HIPCHK(c, hipMalloc(reinterpret_cast<void**>(&c->mms_vals), 6 * size_t(Q) * Q * Q * 8));
-  if (!c->mms_part) HIPCHK(c, hipMalloc(reinterpret_cast<void**>(&c->mms_part), 2048 * 4 * 8));
+  if (!c->mms_part)
+    HIPCHK(c, hipMalloc(reinterpret_cast<void**>(&c->mms_part), mms::kMaxErrorBlocks * 4 * 8));
   c->mms_q = q;
   return ADI_OK;
 }
 
-mms::Tables mms_tables(const adi_ctx* c) {
-  const int Q = c->N * c->mms_q, p = c->p;
-  mms::Tables tb{};
-  tb.x = c->mms_tab;
-  tb.w = c->mms_tab + Q;
-  tb.bv = c->mms_tab + 2 * Q;
-  tb.bd = c->mms_tab + 2 * Q + size_t(Q) * (p + 1);
-  tb.N = c->N;
-  tb.p = p;
-  tb.q = c->mms_q;
-  return tb;
+mms::Tables mms_tables(const adi_ctx* c) { return tables_at(c->mms_tab, c->N, c->p, c->mms_q); }
+
+// Sum the per-block partial sums of the error kernel (in block order) into
+// out: ||E_h - E||, its H(curl) norm, the same for H.
+void errors_from_partials(const std::vector<double>& part, int nblk, double* out) {
+  double sum[4] = {0, 0, 0, 0};
+  for (int b = 0; b < nblk; ++b)
+    for (int k = 0; k < 4; ++k) sum[k] += part[size_t(b) * 4 + k];
+  out[0] = std::sqrt(sum[0]);
+  out[1] = std::sqrt(sum[0] + sum[1]);
+  out[2] = std::sqrt(sum[2]);
+  out[3] = std::sqrt(sum[2] + sum[3]);
 }
 
 // (M (x) M (x) M)^-1 on the three components of buf (E or H boundary rows).
@@ -1359,6 +1361,27 @@ hipError_t enqueue_mass_solves(adi_ctx* c, int kindH, void* buf, hipStream_t s) 
   return hipSuccess;
 }
 
+// State = L2 projection of the six component fields held at the Gauss points
+// in c->mms_vals (projection right-hand sides, then mass solves), time t.
+int project_from_vals(adi_ctx* c, double t, hipStream_t s) {
+  const mms::Tables tb = mms_tables(c);
+  hipError_t e;
+  if (c->esz == 8) {
+    e = mms::launch_project_rhs<double>(tb, c->mms_vals, static_cast<double*>(c->B[0]), s);
+    if (e == hipSuccess) e = enqueue_mass_solves<double>(c, 0, c->B[0], s);
+    if (e == hipSuccess) e = enqueue_mass_solves<double>(c, 1, c->B[1], s);
+  } else {
+    e = mms::launch_project_rhs<float>(tb, c->mms_vals, static_cast<float*>(c->B[0]), s);
+    if (e == hipSuccess) e = enqueue_mass_solves<float>(c, 0, c->B[0], s);
+    if (e == hipSuccess) e = enqueue_mass_solves<float>(c, 1, c->B[1], s);
+  }
+  HIPCHK(c, e);
+  HIPCHK(c, hipMemcpyAsync(c->d_t, &t, 8, hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  c->t = t;
+  return ADI_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1368,24 +1391,21 @@ int adi_mms_project(adi_ctx* c, int q, double t) {
   if (!c->factored) return fail(c, ADI_ESTATE, "adi_factor first");
   int st = mms_ready(c, q);
   if (st != ADI_OK) return st;
-  const mms::Tables tb = mms_tables(c);
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  HIPCHK(c, mms::launch_exact(tb, t, c->mms_vals, c->cap));
-  hipError_t e;
-  if (c->esz == 8) {
-    e = mms::launch_project_rhs<double>(tb, c->mms_vals, static_cast<double*>(c->B[0]), c->cap);
-    if (e == hipSuccess) e = enqueue_mass_solves<double>(c, 0, c->B[0], c->cap);
-    if (e == hipSuccess) e = enqueue_mass_solves<double>(c, 1, c->B[1], c->cap);
-  } else {
-    e = mms::launch_project_rhs<float>(tb, c->mms_vals, static_cast<float*>(c->B[0]), c->cap);
-    if (e == hipSuccess) e = enqueue_mass_solves<float>(c, 0, c->B[0], c->cap);
-    if (e == hipSuccess) e = enqueue_mass_solves<float>(c, 1, c->B[1], c->cap);
-  }
-  HIPCHK(c, e);
-  HIPCHK(c, hipMemcpyAsync(c->d_t, &t, 8, hipMemcpyHostToDevice, c->cap));
-  HIPCHK(c, hipStreamSynchronize(c->cap));
-  c->t = t;
-  return ADI_OK;
+  HIPCHK(c, mms::launch_exact(mms_tables(c), t, c->mms_vals, c->cap));
+  return project_from_vals(c, t, c->cap);
+}
+
+int adi_project(adi_ctx* c, const double* vals_qp, int q, double t) {
+  if (!c || !vals_qp || !std::isfinite(t)) return ADI_EINVAL;
+  if (!c->factored) return fail(c, ADI_ESTATE, "adi_factor first");
+  int st = mms_ready(c, q);
+  if (st != ADI_OK) return st;
+  const size_t Q = size_t(c->N) * q, count = 6 * Q * Q * Q;
+  if (!finite_all(vals_qp, count)) return fail(c, ADI_ENONFINITE, "value not finite");
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, hipMemcpy(c->mms_vals, vals_qp, count * 8, hipMemcpyHostToDevice));
+  return project_from_vals(c, t, c->cap);
 }
 
 int adi_mms_errors(adi_ctx* c, int q, double* out) {
@@ -1404,13 +1424,7 @@ int adi_mms_errors(adi_ctx* c, int q, double* out) {
   HIPCHK(c, hipMemcpyAsync(part.data(), c->mms_part, part.size() * 8, hipMemcpyDeviceToHost,
                            c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  double sum[4] = {0, 0, 0, 0};
-  for (int b = 0; b < nblk; ++b)
-    for (int k = 0; k < 4; ++k) sum[k] += part[size_t(b) * 4 + k];
-  out[0] = std::sqrt(sum[0]);
-  out[1] = std::sqrt(sum[0] + sum[1]);
-  out[2] = std::sqrt(sum[2]);
-  out[3] = std::sqrt(sum[2] + sum[3]);
+  errors_from_partials(part, nblk, out);
   return ADI_OK;
 }
 

@@ -57,8 +57,11 @@ enum RhsStage : int {
   kStageE2 = 1,   // E right-hand sides, substep 2 (eq. discrete3)
   kStageH1 = 2,   // H right-hand sides, substep 1 (eq. discrete2)
   kStageH2 = 3,   // H right-hand sides, substep 2 (eq. discrete4)
-  kStageQ1 = 6,   // E residual b - P x of substep 1 from a given float64 b
-  kStageQ2 = 7,   // the same for substep 2
+  kStageEd1 = 8,  // E increments, substep 1: b - P E (b of eq. discrete1, P the
+                  // row-scaled system matrix of eq. dupa1ab)
+  kStageEd2 = 9,  // the same for substep 2 (eq. discrete3)
+  kStageHd1 = 10, // H increments, substep 1: b - M H (eq. discrete2)
+  kStageHd2 = 11, // the same for substep 2 (eq. discrete4)
 };
 
 struct SourceArgs {
@@ -70,12 +73,12 @@ struct SourceArgs {
 
 template <typename T>
 struct RhsArgs {
-  const void* f[9];       // input fields (E stage: E1..E3,H1..H3; H stage: H1..H3,
-                          // E_old1..3, E_new1..3; residual: E1..E3,H1..H3,X1..X3)
-  void* out[3];           // T (or float for the residual in refine mode)
-  void* out2[3];          // optional second copy of the E outputs, float32
-  const double* bin[3];   // Q stages: the float64 right-hand sides b
-  const T* coef[3];       // E: gamma, beta, alpha ; H: delta; Q: -, -, alpha
+  const void* f[9];       // input fields (E stages: E1..E3,H1..H3; H stages: H1..H3,
+                          // E_old1..3, E_new1..3), in the kernel's input type
+  void* out[3];           // outputs, in the kernel's output type
+  const void* coef[3];    // per-row coefficients, in the kernel's coefficient type:
+                          // E: gamma, beta, alpha (increments: gamma - 1, beta,
+                          // alpha); H: delta
   const T* band;          // [op][r][2p+1], op 0 = M, 1 = A, 2 = B, 3 = S
   const T* zw;            // [op][k][2p+1]: weight of input plane k on output plane
                           // k - p + q (band entry Z[k-p+q][k], zero outside)
@@ -124,11 +127,10 @@ struct FactorArgs {
 // Launchers (kernels.hip).  All enqueue on `stream` and return hipError_t.
 template <typename T>
 hipError_t launch_rhs(int stage, int p, const RhsArgs<T>& a, hipStream_t stream);
-hipError_t launch_residual(int stage, int p, const RhsArgs<double>& a, hipStream_t stream);
-// Right-hand sides in float64 arithmetic from float32 fields: E stages with
-// float64 outputs (out) and their float32 copies (out2), H stages with
-// float32 outputs.
-hipError_t launch_rhs_e64(int stage, int p, const RhsArgs<double>& a, hipStream_t stream);
+// Increments of the float32 mode (stages Ed1/Ed2/Hd1/Hd2): float32 fields and
+// coefficients, float64 arithmetic (bands and z weights in float64), float32
+// outputs.
+hipError_t launch_rhs_inc(int stage, int p, const RhsArgs<double>& a, hipStream_t stream);
 template <typename T>
 hipError_t launch_sweep(int p, int ndesc, const SweepArgs& a, hipStream_t stream);
 hipError_t launch_factor(int p, const FactorArgs& a, hipStream_t stream);

@@ -28,19 +28,31 @@ constexpr int OM = 0, OA = 1, OB = 2, OS = 3;
 //  E stages (fields E1,E2,E3,H1,H2,H3; groups gamma, beta, alpha):
 //    discrete1 / dupa1ab: RE1 = g MMM E1 + b (MAM H3 - MMA H2) + a ABM E2, ...
 //    discrete3:           alpha terms AMB E3, BAM E1, MBA E2.
+//  E increment stages (groups gamma - 1, beta, alpha): the same terms minus
+//    the row-scaled system matrix applied to the old E_c, i.e. b - P E with
+//    P = MMM + alpha (S on the modified axis); the MMM part folds into the
+//    group coefficient gamma - 1, the stiffness part is one more term:
+//    substep 1: - a MSM E1, - a MMS E2, - a SMM E3; substep 2: - a MMS E1,
+//    - a SMM E2, - a MSM E3.
 //  H stages (fields H1..3, E_old1..3, E_new1..3; groups 1, delta):
 //    discrete2: RH1 = MMM H1 - d MAM E3 + d MMA E2', ...
 //    discrete4: RH1 = MMM H1 + d MMA E2' - d MAM E3'', ... (sign of scheme1d)
-//  Q stages (fields X; groups alpha, 1): a given float64 right-hand side b
-//    minus (M..M) X minus alpha (..S..) X.
+//  H increment stages: the delta terms alone (b - MMM H).
 template <int STAGE>
 struct StageInfo;
-template <> struct StageInfo<kStageE1> { static constexpr int NT = 12, NF = 6, NG = 3; };
-template <> struct StageInfo<kStageE2> { static constexpr int NT = 12, NF = 6, NG = 3; };
-template <> struct StageInfo<kStageH1> { static constexpr int NT = 9, NF = 9, NG = 2; };
-template <> struct StageInfo<kStageH2> { static constexpr int NT = 9, NF = 9, NG = 2; };
-template <> struct StageInfo<kStageQ1> { static constexpr int NT = 6, NF = 3, NG = 4; };
-template <> struct StageInfo<kStageQ2> { static constexpr int NT = 6, NF = 3, NG = 4; };
+template <> struct StageInfo<kStageE1> { static constexpr int NT = 12, NG = 3; };
+template <> struct StageInfo<kStageE2> { static constexpr int NT = 12, NG = 3; };
+template <> struct StageInfo<kStageEd1> { static constexpr int NT = 15, NG = 3; };
+template <> struct StageInfo<kStageEd2> { static constexpr int NT = 15, NG = 3; };
+template <> struct StageInfo<kStageH1> { static constexpr int NT = 9, NG = 2; };
+template <> struct StageInfo<kStageH2> { static constexpr int NT = 9, NG = 2; };
+template <> struct StageInfo<kStageHd1> { static constexpr int NT = 6, NG = 2; };
+template <> struct StageInfo<kStageHd2> { static constexpr int NT = 6, NG = 2; };
+
+template <int STAGE>
+constexpr bool is_h_stage() {
+  return STAGE == kStageH1 || STAGE == kStageH2 || STAGE == kStageHd1 || STAGE == kStageHd2;
+}
 
 template <int STAGE>
 __host__ __device__ constexpr Term get_term(int i) {
@@ -52,15 +64,12 @@ __host__ __device__ constexpr Term get_term(int i) {
                               {2, 2, +1, 0, OB, OM, OA}};
   constexpr Term r_sub2[3] = {{0, 2, +1, 2, OA, OM, OB}, {1, 2, +1, 0, OB, OA, OM},
                               {2, 2, +1, 1, OM, OB, OA}};
-  // minus the product operator applied to X: mass part and the stiffness
-  // part on the modified axis (substep 1: E1 y, E2 z, E3 x; substep 2: E1 z,
-  // E2 x, E3 y)
-  constexpr Term px_sub1[6] = {{0, 3, -1, 6, OM, OM, OM}, {0, 2, -1, 6, OM, OS, OM},
-                               {1, 3, -1, 7, OM, OM, OM}, {1, 2, -1, 7, OM, OM, OS},
-                               {2, 3, -1, 8, OM, OM, OM}, {2, 2, -1, 8, OS, OM, OM}};
-  constexpr Term px_sub2[6] = {{0, 3, -1, 6, OM, OM, OM}, {0, 2, -1, 6, OM, OM, OS},
-                               {1, 3, -1, 7, OM, OM, OM}, {1, 2, -1, 7, OS, OM, OM},
-                               {2, 3, -1, 8, OM, OM, OM}, {2, 2, -1, 8, OM, OS, OM}};
+  // stiffness part of P E_c on the modified axis (substep 1: E1 y, E2 z,
+  // E3 x; substep 2: E1 z, E2 x, E3 y)
+  constexpr Term s_sub1[3] = {{0, 2, -1, 0, OM, OS, OM}, {1, 2, -1, 1, OM, OM, OS},
+                              {2, 2, -1, 2, OS, OM, OM}};
+  constexpr Term s_sub2[3] = {{0, 2, -1, 0, OM, OM, OS}, {1, 2, -1, 1, OS, OM, OM},
+                              {2, 2, -1, 2, OM, OS, OM}};
   constexpr Term h_sub1[9] = {
       {0, 0, +1, 0, OM, OM, OM}, {0, 1, -1, 5, OM, OA, OM}, {0, 1, +1, 7, OM, OM, OA},
       {1, 0, +1, 1, OM, OM, OM}, {1, 1, -1, 3, OM, OM, OA}, {1, 1, +1, 8, OA, OM, OM},
@@ -71,25 +80,28 @@ __host__ __device__ constexpr Term get_term(int i) {
       {2, 0, +1, 2, OM, OM, OM}, {2, 1, +1, 3, OM, OA, OM}, {2, 1, -1, 7, OA, OM, OM}};
   if (STAGE == kStageH1) return h_sub1[i];
   if (STAGE == kStageH2) return h_sub2[i];
-  if (STAGE == kStageQ1 || STAGE == kStageQ2) {  // the product-operator terms alone, on X1..X3
-    Term t = STAGE == kStageQ1 ? px_sub1[i] : px_sub2[i];
-    t.field -= 6;
-    return t;
-  }
+  if (STAGE == kStageHd1) return h_sub1[i + 1 + i / 2];  // the two delta terms of each output
+  if (STAGE == kStageHd2) return h_sub2[i + 1 + i / 2];
   if (i < 9) return curl_and_mass[i];
-  return STAGE == kStageE2 ? r_sub2[i - 9] : r_sub1[i - 9];
+  constexpr bool sub2 = STAGE == kStageE2 || STAGE == kStageEd2;
+  if (i < 12) return sub2 ? r_sub2[i - 9] : r_sub1[i - 9];
+  return sub2 ? s_sub2[i - 12] : s_sub1[i - 12];
 }
 
 // Per output component: the input fields it reads (local slots) and its
-// distinct (field, y-operator) pairs, each applied once per plane.
+// distinct (field, y-operator) pairs, each applied once per plane.  The y
+// pass gives each field slot one wave, which applies the pairs of that
+// field (at most two) to the same loaded column values.
 struct CompTab {
   int nf[3] = {};           // fields read by component c
   int field[3][8] = {};     // slot -> field index
   int np[3] = {};           // pairs of component c
-  int pslot[3][12] = {};    // pair -> field slot
-  int pyop[3][12] = {};     // pair -> y operator
+  int pslot[3][16] = {};    // pair -> field slot
+  int pyop[3][16] = {};     // pair -> y operator
+  int nsp[3][8] = {};       // slot -> number of its pairs
+  int spair[3][8][2] = {};  // slot -> its pairs
   int term_pair[24] = {};   // term -> pair index within its component
-  int maxnf = 0, maxnp = 0;
+  int maxnf = 0, maxnp = 0, maxsp = 0;
 };
 
 template <int STAGE>
@@ -112,12 +124,14 @@ constexpr CompTab make_comp_tab() {
       pr = t.np[c]++;
       t.pslot[c][pr] = slot;
       t.pyop[c][pr] = tm.y;
+      t.spair[c][slot][t.nsp[c][slot]++] = pr;
     }
     t.term_pair[i] = pr;
   }
   for (int c = 0; c < 3; ++c) {
     t.maxnf = t.nf[c] > t.maxnf ? t.nf[c] : t.maxnf;
     t.maxnp = t.np[c] > t.maxnp ? t.np[c] : t.maxnp;
+    for (int k = 0; k < t.nf[c]; ++k) t.maxsp = t.nsp[c][k] > t.maxsp ? t.nsp[c][k] : t.maxsp;
   }
   return t;
 }
@@ -135,20 +149,13 @@ constexpr int kTX = 32, kTY = 8, kCols = kTX * kTY;
 constexpr int kXcds = 8;  // MI355X: 8 accelerator complex dies, one L2 each
 constexpr int kRhsThreads = kCols;  // one block per (tile, output component)
 
-// The Q stages keep four accumulator groups per thread; their x band rows
-// are read from LDS instead of registers to stay clear of spills.
-template <int STAGE>
-constexpr bool xband_in_lds() { return StageInfo<STAGE>::NG == 4; }
-
-// LDS of one RHS block: y-pass results (two buffers), x band rows (Q
-// stages), the y band rows of the tile and the z weights of the chunk's
-// input planes.
+// LDS of one RHS block: y-pass results (two buffers), the y band rows of
+// the tile and the z weights of the chunk's input planes.
 template <typename TC, int P, int STAGE>
 size_t rhs_lds_bytes(int zchunk) {
   constexpr int HX = kTX + 2 * P, W = 2 * P + 1;
   constexpr CompTab CT = make_comp_tab<STAGE>();
-  return sizeof(TC) * (2 * size_t(CT.maxnp) * kTY * HX +
-                       (xband_in_lds<STAGE>() ? 4 * kTX * W : 0) + size_t(4) * kTY * W +
+  return sizeof(TC) * (2 * size_t(CT.maxnp) * kTY * HX + size_t(4) * kTY * W +
                        size_t(zchunk + 2 * P) * 4 * W);
 }
 
@@ -165,28 +172,27 @@ size_t rhs_lds_bytes(int zchunk) {
 // registers, and each result is scattered into a register queue of 2p+1
 // pending output planes with the z operator's weights.  When the oldest
 // pending plane is complete it is scaled by the per-row coefficients and
-// written.  TI: input type, TC: arithmetic type, TO: output type.
-template <typename TI, typename TC, typename TO, int P, int STAGE>
+// written.  TI: input type, TC: arithmetic type, TO: output type, TK:
+// coefficient type.
+template <typename TI, typename TC, typename TO, typename TK, int P, int STAGE>
 __global__ __launch_bounds__(kRhsThreads) void rhs_kernel(RhsArgs<TC> a,
                                                           const TC* __restrict__ band,
                                                           const TC* __restrict__ zw) {
   constexpr int W = 2 * P + 1, HX = kTX + 2 * P, HY = kTY + 2 * P;
   constexpr int NT = StageInfo<STAGE>::NT, NG = StageInfo<STAGE>::NG;
   constexpr CompTab CT = make_comp_tab<STAGE>();
-  constexpr bool kE = !(STAGE == kStageH1 || STAGE == kStageH2);
-  constexpr bool kQ = STAGE == kStageQ1 || STAGE == kStageQ2;
+  constexpr bool kE = !is_h_stage<STAGE>();
   constexpr int NWAVES = kRhsThreads / 64;
-  static_assert(CT.maxnp <= NWAVES, "one (field, y operator) pair per wave");
+  static_assert(CT.maxnf <= NWAVES, "one field per wave in the y pass");
+  static_assert(CT.maxsp <= 2, "at most two y operators per field");
   static_assert(HX <= 64, "one lane per x column in the y pass");
   constexpr int GSZ = CT.maxnp * kTY * HX;  // one y-pass buffer
   constexpr int NCF = kE ? 3 : 1;           // per-row coefficients of an output
 
   extern __shared__ __align__(16) unsigned char smem[];
   TC* sG = reinterpret_cast<TC*>(smem);  // [2][pair][yy][x]
-  constexpr bool kXL = xband_in_lds<STAGE>();
-  TC* sBX = sG + 2 * GSZ;                   // x band rows (Q stages only)
-  TC* sYB = sBX + (kXL ? 4 * kTX * W : 0);  // y band rows [op][yy][d] of the tile
-  TC* sZW = sYB + 4 * kTY * W;              // z weights [plane - kbeg][op][q]
+  TC* sYB = sG + 2 * GSZ;                // y band rows [op][yy][d] of the tile
+  TC* sZW = sYB + 4 * kTY * W;           // z weights [plane - kbeg][op][q]
 
   const int n = a.n;
   const size_t plane = size_t(n) * n;
@@ -218,20 +224,12 @@ __global__ __launch_bounds__(kRhsThreads) void rhs_kernel(RhsArgs<TC> a,
   const int t1 = min(n, t0 + a.zchunk);
   const int i = i0 + tx, j = j0 + ty;
 
-  // x band rows of this thread's output column (registers, or LDS for the
-  // Q stages)
-  TC xb[kXL ? 1 : 4][W];
-  if (kXL) {
-    for (int idx = tid; idx < 4 * kTX * W; idx += kRhsThreads) {
-      const int op = idx / (kTX * W), rem = idx % (kTX * W), r = rem / W, d = rem % W;
-      sBX[idx] = (i0 + r < n) ? band[(size_t(op) * n + i0 + r) * W + d] : TC(0);
-    }
-  } else {
+  // x band rows of this thread's output column (registers)
+  TC xb[4][W];
 #pragma unroll
-    for (int op = 0; op < (kXL ? 1 : 4); ++op)
+  for (int op = 0; op < 4; ++op)
 #pragma unroll
-      for (int d = 0; d < W; ++d) xb[op][d] = (i < n) ? band[(size_t(op) * n + i) * W + d] : TC(0);
-  }
+    for (int d = 0; d < W; ++d) xb[op][d] = (i < n) ? band[(size_t(op) * n + i) * W + d] : TC(0);
 
   // y band rows of the tile and z weights of the chunk's input planes (read
   // by every lane: LDS broadcasts instead of scalar loads in the plane loop)
@@ -245,21 +243,23 @@ __global__ __launch_bounds__(kRhsThreads) void rhs_kernel(RhsArgs<TC> a,
     sZW[idx] = zw[(size_t(op) * n + kbeg + kk) * W + q];
   }
 
-  // This wave's (field, y operator) pair and this lane's column x = i0 - P +
-  // lane, rows y = j0 - P + m (m < HY).  Every global load in the plane loop
-  // is issued unconditionally: columns and rows outside the grid are clamped
-  // to its edge (their band weights are zero, so the values read there never
-  // contribute), a wave without a pair reads a single address, and planes
-  // past the chunk re-read its last one.  With no load skipped by a branch
-  // the compiler counts the loads in flight exactly, and each wait for a
-  // plane or a coefficient leaves the younger prefetches in flight.
-  const int npc = CT.np[comp];
-  const bool on = wave < npc;
-  const int pr = on ? wave : 0;
-  const int pyop = CT.pyop[comp][pr];
+  // This wave's field slot (its one or two y operators) and this lane's
+  // column x = i0 - P + lane, rows y = j0 - P + m (m < HY).  Every global
+  // load in the plane loop is issued unconditionally: columns and rows
+  // outside the grid are clamped to its edge (their band weights are zero,
+  // so the values read there never contribute), a wave without a field reads
+  // a single address, and planes past the chunk re-read its last one.  With
+  // no load skipped by a branch the compiler counts the loads in flight
+  // exactly, and each wait for a plane or a coefficient leaves the younger
+  // prefetches in flight.
+  const bool on = wave < CT.nf[comp];
+  const int slot = on ? wave : 0;
+  const int nsp = on ? CT.nsp[comp][slot] : 0;  // pairs of this wave's field
+  const int pr0 = CT.spair[comp][slot][0], pr1 = CT.spair[comp][slot][1];
+  const int yop0 = CT.pyop[comp][pr0], yop1 = CT.pyop[comp][pr1];
   // Addresses are a block-uniform row or plane pointer plus a 32-bit lane
   // offset (n^2 < 2^31), which keeps one offset register per lane.
-  const TI* fsrc = static_cast<const TI*>(a.f[CT.field[comp][CT.pslot[comp][pr]]]);
+  const TI* fsrc = static_cast<const TI*>(a.f[CT.field[comp][slot]]);
   const unsigned loff = on ? unsigned(min(max(i0 - P + lane, 0), n - 1)) : 0u;
   const size_t pstride = on ? plane : 0;
   int rows[HY];
@@ -275,11 +275,7 @@ __global__ __launch_bounds__(kRhsThreads) void rhs_kernel(RhsArgs<TC> a,
   auto load_cf = [&](int te, TC (&c)[NCF]) {
     const size_t po = plane * size_t(min(max(te, 0), n - 1));
 #pragma unroll
-    for (int q = 0; q < NCF; ++q) {
-      if (kQ && q == 0) c[q] = TC((a.bin[comp] + po)[colo]);
-      else if (kQ && q == 1) c[q] = TC(0);
-      else c[q] = (a.coef[q] + po)[colo];
-    }
+    for (int q = 0; q < NCF; ++q) c[q] = TC((static_cast<const TK*>(a.coef[q]) + po)[colo]);
   };
 
   TC acc[NG][W];
@@ -292,7 +288,7 @@ __global__ __launch_bounds__(kRhsThreads) void rhs_kernel(RhsArgs<TC> a,
   // basis values (zero for columns outside the source's support)
   double jsrc = 0.0;
   bool srccol = false;
-  if (!kQ && kE && a.src.comp == comp) {
+  if (kE && a.src.comp == comp) {
     const int ri = i - a.src.first[0], rj = j - a.src.first[1];
     srccol = ri >= 0 && ri <= P && rj >= 0 && rj <= P;
     const double tm = *a.tnow + a.frac_dt;
@@ -310,16 +306,14 @@ __global__ __launch_bounds__(kRhsThreads) void rhs_kernel(RhsArgs<TC> a,
                bk = (te == 0 || te == n - 1);
     if (kE) {
       const TC g = cf[0], b = cf[kE ? 1 : 0], al = cf[kE ? 2 : 0];
-      TC v = kQ ? g + al * acc[2][0] : g * acc[0][0] + b * acc[1][0] + al * acc[2][0];
-      if (NG == 4) v += acc[NG - 1][0];
-      if (!kQ && srccol) {
+      TC v = g * acc[0][0] + b * acc[1][0] + al * acc[2 % NG][0];
+      if (srccol) {
         const int rk = te - a.src.first[2];
         if (rk >= 0 && rk <= P) v -= b * TC(jsrc * a.src.bz[rk]);
       }
       // E_c is constrained on the faces normal to the two other axes
       const bool bnd = (comp == 0) ? (bj || bk) : (comp == 1) ? (bi || bk) : (bi || bj);
       (static_cast<TO*>(a.out[comp]) + po)[o] = bnd ? TO(0) : TO(v);
-      if (a.out2[comp]) (static_cast<float*>(a.out2[comp]) + po)[o] = bnd ? 0.0f : float(v);
     } else {
       const TC v = acc[0][0] + cf[0] * acc[1][0];
       // H_c is constrained on the faces normal to axis c
@@ -354,15 +348,25 @@ __global__ __launch_bounds__(kRhsThreads) void rhs_kernel(RhsArgs<TC> a,
     const int te = k - P;
     load_cf(te + 1, cfr[S ^ 1]);
     TC* G = sG + S * GSZ;
-    // y pass from registers
+    // y pass from registers: the wave's one or two y operators on its field
     if (on && lane < HX) {
-      const TC* yb0 = sYB + pyop * kTY * W;
+      const TC* yb0 = sYB + yop0 * kTY * W;
 #pragma unroll
       for (int yy = 0; yy < kTY; ++yy) {
         TC s = TC(0);
 #pragma unroll
         for (int d = 0; d < W; ++d) s += yb0[yy * W + d] * TC(pre[S][yy + d]);
-        G[(wave * kTY + yy) * HX + lane] = s;
+        G[(pr0 * kTY + yy) * HX + lane] = s;
+      }
+      if (CT.maxsp > 1 && nsp > 1) {  // wave-uniform
+        const TC* yb1 = sYB + yop1 * kTY * W;
+#pragma unroll
+        for (int yy = 0; yy < kTY; ++yy) {
+          TC s = TC(0);
+#pragma unroll
+          for (int d = 0; d < W; ++d) s += yb1[yy * W + d] * TC(pre[S][yy + d]);
+          G[(pr1 * kTY + yy) * HX + lane] = s;
+        }
       }
     }
     load_plane(k + 2, pre[S]);
@@ -375,10 +379,7 @@ __global__ __launch_bounds__(kRhsThreads) void rhs_kernel(RhsArgs<TC> a,
       if (tm.out == comp) {
         TC v = TC(0);
 #pragma unroll
-        for (int d = 0; d < W; ++d) {
-          const TC xw = kXL ? sBX[(tm.x * kTX + tx) * W + d] : xb[kXL ? 0 : tm.x][d];
-          v += xw * G[(tp * kTY + ty) * HX + tx + d];
-        }
+        for (int d = 0; d < W; ++d) v += xb[tm.x][d] * G[(tp * kTY + ty) * HX + tx + d];
         if (tm.sign < 0) v = -v;
         const TC* zq = zk + tm.z * W;
 #pragma unroll
@@ -499,8 +500,6 @@ __device__ __forceinline__ void sweep_body(const SweepArgs& a) {
 
   // x lines: copy columns [c0, c1) of the nll contiguous lines into
   // buf[(r - c0) * PIT + line] (coalesced global reads)
-  const float inv_w = 1.0f;  // placeholder to keep the lambda signature simple
-  (void)inv_w;
   auto stage_cols = [&](int c0, int c1) {
     const int wdt = c1 - c0, total = nll * wdt;
     const float inv = 1.0f / float(wdt);
@@ -1179,9 +1178,9 @@ hipError_t set_lds(K kernel, size_t bytes) {
                              hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
 }
 
-template <typename TI, typename TC, typename TO, int P, int STAGE>
+template <typename TI, typename TC, typename TO, typename TK, int P, int STAGE>
 hipError_t launch_rhs_t(const RhsArgs<TC>& a, hipStream_t s) {
-  auto k = rhs_kernel<TI, TC, TO, P, STAGE>;
+  auto k = rhs_kernel<TI, TC, TO, TK, P, STAGE>;
   const size_t lds = rhs_lds_bytes<TC, P, STAGE>(a.zchunk);
   hipError_t e = set_lds(k, lds);
   if (e != hipSuccess) return e;
@@ -1191,44 +1190,24 @@ hipError_t launch_rhs_t(const RhsArgs<TC>& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <typename TI, typename TC, typename TO, int P>
-hipError_t launch_rhs_p(int stage, const RhsArgs<TC>& a, hipStream_t s) {
+template <typename T, int P>
+hipError_t launch_rhs_p(int stage, const RhsArgs<T>& a, hipStream_t s) {
   switch (stage) {
-    case kStageE1: return launch_rhs_t<TI, TC, TO, P, kStageE1>(a, s);
-    case kStageE2: return launch_rhs_t<TI, TC, TO, P, kStageE2>(a, s);
-    case kStageH1: return launch_rhs_t<TI, TC, TO, P, kStageH1>(a, s);
-    case kStageH2: return launch_rhs_t<TI, TC, TO, P, kStageH2>(a, s);
+    case kStageE1: return launch_rhs_t<T, T, T, T, P, kStageE1>(a, s);
+    case kStageE2: return launch_rhs_t<T, T, T, T, P, kStageE2>(a, s);
+    case kStageH1: return launch_rhs_t<T, T, T, T, P, kStageH1>(a, s);
+    case kStageH2: return launch_rhs_t<T, T, T, T, P, kStageH2>(a, s);
   }
   return hipErrorInvalidValue;
 }
 
 template <int P>
-hipError_t launch_res_p(int stage, const RhsArgs<double>& a, hipStream_t s) {
+hipError_t launch_inc_p(int stage, const RhsArgs<double>& a, hipStream_t s) {
   switch (stage) {
-    case kStageQ1: return launch_rhs_t<float, double, float, P, kStageQ1>(a, s);
-    case kStageQ2: return launch_rhs_t<float, double, float, P, kStageQ2>(a, s);
-  }
-  return hipErrorInvalidValue;
-}
-
-template <int P>
-hipError_t launch_e64_p(int stage, const RhsArgs<double>& a, hipStream_t s) {
-  switch (stage) {
-    case kStageE1: return launch_rhs_t<float, double, double, P, kStageE1>(a, s);
-    case kStageE2: return launch_rhs_t<float, double, double, P, kStageE2>(a, s);
-    case kStageH1: return launch_rhs_t<float, double, float, P, kStageH1>(a, s);
-    case kStageH2: return launch_rhs_t<float, double, float, P, kStageH2>(a, s);
-  }
-  return hipErrorInvalidValue;
-}
-
-template <typename TI, typename TC, typename TO>
-hipError_t launch_rhs_any(int stage, int p, const RhsArgs<TC>& a, hipStream_t s) {
-  switch (p) {
-    case 1: return launch_rhs_p<TI, TC, TO, 1>(stage, a, s);
-    case 2: return launch_rhs_p<TI, TC, TO, 2>(stage, a, s);
-    case 3: return launch_rhs_p<TI, TC, TO, 3>(stage, a, s);
-    case 4: return launch_rhs_p<TI, TC, TO, 4>(stage, a, s);
+    case kStageEd1: return launch_rhs_t<float, double, float, float, P, kStageEd1>(a, s);
+    case kStageEd2: return launch_rhs_t<float, double, float, float, P, kStageEd2>(a, s);
+    case kStageHd1: return launch_rhs_t<float, double, float, float, P, kStageHd1>(a, s);
+    case kStageHd2: return launch_rhs_t<float, double, float, float, P, kStageHd2>(a, s);
   }
   return hipErrorInvalidValue;
 }
@@ -1328,29 +1307,25 @@ hipError_t launch_sweep_p(int ndesc, const SweepArgs& a, hipStream_t s) {
 
 template <typename T>
 hipError_t launch_rhs(int stage, int p, const RhsArgs<T>& a, hipStream_t s) {
-  return launch_rhs_any<T, T, T>(stage, p, a, s);
+  switch (p) {
+    case 1: return launch_rhs_p<T, 1>(stage, a, s);
+    case 2: return launch_rhs_p<T, 2>(stage, a, s);
+    case 3: return launch_rhs_p<T, 3>(stage, a, s);
+    case 4: return launch_rhs_p<T, 4>(stage, a, s);
+  }
+  return hipErrorInvalidValue;
 }
 template hipError_t launch_rhs<double>(int, int, const RhsArgs<double>&, hipStream_t);
 template hipError_t launch_rhs<float>(int, int, const RhsArgs<float>&, hipStream_t);
 
-hipError_t launch_rhs_e64(int stage, int p, const RhsArgs<double>& a, hipStream_t s) {
+// Increments of the float32 mode: float32 fields and coefficients, float64
+// arithmetic, float32 outputs.
+hipError_t launch_rhs_inc(int stage, int p, const RhsArgs<double>& a, hipStream_t s) {
   switch (p) {
-    case 1: return launch_e64_p<1>(stage, a, s);
-    case 2: return launch_e64_p<2>(stage, a, s);
-    case 3: return launch_e64_p<3>(stage, a, s);
-    case 4: return launch_e64_p<4>(stage, a, s);
-  }
-  return hipErrorInvalidValue;
-}
-
-// float64 residual of the float32 E solve: inputs float32, arithmetic float64,
-// output float32 (the residual is small; float32 keeps ~7 digits of it).
-hipError_t launch_residual(int stage, int p, const RhsArgs<double>& a, hipStream_t s) {
-  switch (p) {
-    case 1: return launch_res_p<1>(stage, a, s);
-    case 2: return launch_res_p<2>(stage, a, s);
-    case 3: return launch_res_p<3>(stage, a, s);
-    case 4: return launch_res_p<4>(stage, a, s);
+    case 1: return launch_inc_p<1>(stage, a, s);
+    case 2: return launch_inc_p<2>(stage, a, s);
+    case 3: return launch_inc_p<3>(stage, a, s);
+    case 4: return launch_inc_p<4>(stage, a, s);
   }
   return hipErrorInvalidValue;
 }

@@ -158,7 +158,9 @@ __global__ __launch_bounds__(256) void errors_kernel(Tables tb, const T* __restr
   if (threadIdx.x < 4) partial[blockIdx.x * 4 + threadIdx.x] = red[threadIdx.x][0];
 }
 
-int grid_for(size_t work) { return int(std::min<size_t>((work + 255) / 256, 2048)); }
+int grid_for(size_t work) {
+  return int(std::min<size_t>((work + 255) / 256, size_t(kMaxErrorBlocks)));
+}
 
 }  // namespace
 

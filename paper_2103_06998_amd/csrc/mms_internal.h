@@ -9,6 +9,8 @@ namespace mms {
 // Quadrature tables of one axis: Q = N q Gauss points, for point a the
 // basis functions a/q .. a/q + p (element a/q) with values bv[a*(p+1) + r]
 // and derivatives bd[a*(p+1) + r]; coordinates x[a] and weights w[a].
+constexpr int kMaxErrorBlocks = 2048;
+
 struct Tables {
   const double* x;
   const double* w;
@@ -26,7 +28,8 @@ template <typename T>
 hipError_t launch_project_rhs(const Tables& tb, const double* vals, T* state, hipStream_t s);
 // Per-block partial sums of the squared errors of the state against the
 // manufactured solution at time t: [block][0] E L2, [1] E curl, [2] H L2,
-// [3] H curl.  Returns the number of blocks written (nblk <= max_blocks).
+// [3] H curl.  Returns the number of blocks written (nblk <= kMaxErrorBlocks);
+// every block writes its four sums (nothing needs clearing).
 template <typename T>
 hipError_t launch_errors(const Tables& tb, const T* state, double t, double* partial,
                          int* nblk, hipStream_t s);

@@ -9,9 +9,9 @@ FETCH_DIR / WRITE_DIR hold the run_counter_collection.csv of a
 `python -m paper_2103_06998_amd.profile_step --precision PRECISION`.  Both
 counters are in KiB per dispatch; each is scaled by (copy bytes) / (what the
 counter reads for the copy dispatch of that run), then averaged per launch
-over the dispatches of each kernel class.  The result is merged into the
-output JSON under "<precision>:<class>" together with the sha256 of the
-kernel source it was measured on.
+over the dispatches of each kernel.  The result is merged into the output
+JSON under "<precision>:<kernel>" (the kernel's name without namespace and
+arguments) together with the sha256 of the kernel source it was measured on.
 """
 from __future__ import annotations
 
@@ -28,19 +28,13 @@ ROOT = os.path.dirname(HERE)
 
 
 def kernel_class(name: str):
-    m = re.search(r"rhs_kernel<[^>]*?,\s*(\d+)>\(", name)
-    if m:
-        stage = int(m.group(1))
-        return {0: "rhs_E", 1: "rhs_E", 2: "rhs_H", 3: "rhs_H", 6: "residual64",
-                7: "residual64"}.get(stage)
-    if re.search(r"(sweep|spike)_mixed_kernel<", name):
-        return "sweep_xyz"
-    m = re.search(r"(sweep|spike)_kernel<\w+, \d+, (true|false)", name)
-    if m:
-        return "sweep_x" if m.group(2) == "true" else "sweep_yz"
+    """Kernel name without namespace and arguments (e.g.
+    "sweep_mixed_kernel<float, 3, true>"), "copy" for the runtime's copy
+    kernel, None for anything else."""
     if "copyBuffer" in name:
         return "copy"
-    return None
+    m = re.search(r"(\w+_kernel<[^()]*>)\(", name)
+    return m.group(1) if m else None
 
 
 def per_dispatch(path, counter):

@@ -140,11 +140,13 @@ class Solver:
         kind = (ctypes.c_int * cap)()
         nd = (ctypes.c_int * cap)()
         nm = (ctypes.c_int * cap)()
+        na = (ctypes.c_int * cap)()
         ms = (ctypes.c_float * cap)()
         nout = ctypes.c_int()
-        self._check(self.lib.adi_profile_read(self.h, cap, ctypes.byref(nout), kind, nd, nm, ms))
-        return [dict(kind=self.KINDS[kind[i]], ncomp=nd[i], nmod=nm[i], ms=float(ms[i]))
-                for i in range(min(cap, nout.value))]
+        self._check(self.lib.adi_profile_read(self.h, cap, ctypes.byref(nout), kind, nd, nm, na,
+                                              ms))
+        return [dict(kind=self.KINDS[kind[i]], ncomp=nd[i], nmod=nm[i], nacc=na[i],
+                     ms=float(ms[i])) for i in range(min(cap, nout.value))]
 
     # -- single stages (testing) ---------------------------------------------
     def rhs(self, stage: int, sub: int, fields, t: float = 0.0):
@@ -196,6 +198,13 @@ class Solver:
     def mms_project(self, q: int = 0, t: float = 0.0):
         """State = L2 projection of the manufactured solution at time t."""
         self._check(self.lib.adi_mms_project(self.h, int(q or self.p + 3), float(t)))
+
+    def project(self, vals_qp, q: int, t: float = 0.0):
+        """State = L2 projection of six component fields given at the Gauss
+        points (array (6, N q, N q, N q), x fastest), time t."""
+        Q = self.N * int(q)
+        a = self._arr(vals_qp, 6 * Q ** 3)
+        self._check(self.lib.adi_project(self.h, _lib.dptr(a), int(q), float(t)))
 
     def mms_errors(self, q: int = 0) -> dict:
         """Absolute L2 and H(curl) errors of E and H against the manufactured

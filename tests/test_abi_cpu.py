@@ -109,3 +109,14 @@ def test_network_host_validation(lib):
     assert lib.adi_nn_param_count(None) == _lib.ADI_EINVAL
     assert lib.adi_copy_state(None, None) == _lib.ADI_EINVAL
     assert lib.adi_step_closure(None, None, 1, ctypes.c_float(0.0)) == _lib.ADI_EINVAL
+
+
+def test_project_host_validation(lib):
+    st, h = _ctx(lib)
+    try:
+        vals = np.zeros(6 * 9 ** 3)
+        assert lib.adi_project(h, _lib.dptr(vals), 3, 0.0) == _lib.ADI_ESTATE
+        assert lib.adi_project(h, None, 3, 0.0) == _lib.ADI_EINVAL
+        assert lib.adi_project(h, _lib.dptr(vals), 3, float("inf")) == _lib.ADI_EINVAL
+    finally:
+        lib.adi_destroy(h)

@@ -4,19 +4,30 @@ Tolerances (relative L2 norm of the difference, per field component):
 * float64 path: 1e-12.  Both sides solve the same well-conditioned banded
   systems (1D condition numbers below ~30) in a different summation order,
   so the differences are a few units of roundoff per step.
-* float32 bulk with float64 factors and one float64 residual correction:
-  1e-5 (the state is stored in float32; each step adds ~1e-7 of rounding).
+* float32 mode (float32 state and sweeps, every stage solved in increment
+  form from a float64 residual of the old state): 1e-5 per component.  The
+  state is stored in float32, which alone (exact solves) adds ~1e-7 of
+  relative rounding per step and field; the float32 sweeps act on the
+  increments, so their rounding scales with the increments.  The one
+  exception is degree 4 from a white-noise state (see its test).
+Besides the relative L2 every comparison checks the element-wise largest
+difference against the component's largest value, which a localized defect
+(a wrong source row, a wrong PEC face) would make of the order of the field
+itself: within 1e-12 for float64, within 5e-5 for the float32 mode, whose
+rounding errors are spread over all D ~ 10^6 coefficients (the largest of D
+such errors exceeds their RMS by about sqrt(2 ln D) ~ 5).
 """
 import numpy as np
 import pytest
 
 import workloads
-from oracle import gram, maxwell, mms
+from oracle import maxwell, mms
 
 pytestmark = pytest.mark.gpu
 
 TOL64 = 1e-12
 TOL32 = 1e-5
+MAXABS_FACTOR32 = 5.0  # element-wise bound of the float32 mode, relative to its L2 bound
 
 
 @pytest.fixture(scope="module")
@@ -59,9 +70,23 @@ def constrained_random_state(prob, seed):
     return E, H
 
 
+def max_abs_rel(a, b):
+    """Largest element-wise difference over the largest reference value."""
+    m = np.abs(b).max()
+    return np.abs(a - b).max() / (m if m > 0 else 1.0)
+
+
 def compare_state(EH_gpu, E, H, tol, label=""):
-    errs = [rel_l2(EH_gpu[c], (E + H)[c]) for c in range(6)]
-    assert max(errs) <= tol, (label, errs)
+    """Per component: relative L2 within tol and element-wise max-abs
+    (against the component's largest value) within tol, or within
+    MAXABS_FACTOR32 * tol for the float32 mode; a localized error (the source
+    rows, a PEC face) cannot hide under the L2 norm."""
+    ref = E + H
+    errs = [rel_l2(EH_gpu[c], ref[c]) for c in range(6)]
+    emax = [max_abs_rel(EH_gpu[c], ref[c]) for c in range(6)]
+    tol_max = tol if tol <= TOL64 else MAXABS_FACTOR32 * tol
+    assert max(errs) <= tol, (label, "relative L2", errs)
+    assert max(emax) <= tol_max, (label, "max-abs", emax)
     return errs
 
 
@@ -157,32 +182,71 @@ def test_large_rounds_two_launches(Solver, precision, tol):
     compare_state(got, E, H, tol, ("n148", precision))
 
 
-@pytest.mark.parametrize("N,p", [(4, 3), (4, 4), (45, 4)])
-def test_full_steps_fp32_refine_random_material(Solver, N, p):
-    """FP32 mode (float32 bulk, float64 right-hand sides and one float64
-    correction of the E solve) on random per-DOF material from a random
-    (rough) state, two steps against the oracle.
-
-    Tolerance from the arithmetic: a step applies three float32 1D solves
-    per field (the H solve without correction), each with a relative error
-    of about kappa(M_1D) * 2^-24 at most, and a rough state excites the
-    worst-conditioned modes; so 2 * steps * 3 * kappa(M_1D) * 2^-24, kappa
-    from the oracle's 1D mass matrix (27 at p = 3, 69-82 at p = 4: 2e-5 and
-    5e-5 for two steps; measured at p = 4, N = 4: 3.9e-5)."""
-    steps = 2
-    kappa = np.linalg.cond(gram.gram_matrices(N, p)[0])
-    tol = 2 * steps * 3 * kappa * 2.0 ** -24
+def _fp32_random_steps(Solver, N, p, steps=2):
     eps, mu, sig, src = random_setup(N, p, seed=200 + N)
     dt = 0.5 / N
     prob = maxwell.Problem(N, p, eps, mu, sig, dt, src)
     s = make_gpu(Solver, N, p, eps, mu, sig, dt, src, "fp32_refine")
-    E, H = constrained_random_state(prob, 21)
-    s.set_fields(np.stack(E + H), 0.01)
+    E0, H0 = constrained_random_state(prob, 21)
+    s.set_fields(np.stack(E0 + H0), 0.01)
     s.step(steps)
-    E, H, t = prob.run(E, H, 0.01, steps)
-    got, _ = s.get_fields()
-    errs = compare_state(got, E, H, tol, ("fp32", N, p, tol))
-    print("fp32 random material", N, p, "tol", tol, "errors", errs)
+    E, H, t = prob.run(E0, H0, 0.01, steps)
+    got, tg = s.get_fields()
+    assert tg == pytest.approx(t, rel=1e-12)
+    return prob, (E0, H0), got, E, H
+
+
+@pytest.mark.parametrize("N", [4, 45, 128])
+def test_full_steps_fp32_refine_random_material(Solver, N):
+    """FP32 mode on random per-DOF material from a random (rough) state, two
+    steps at p = 3 against the oracle, per component within 1e-5.  n = 48
+    and n = 131 run the float32 partitioned sweeps and mixed-axis rounds of
+    the 128^3 workload (n = 131 also wraps the ring of per-line factor
+    chunks of the material-modified sweeps several times)."""
+    _, _, got, E, H = _fp32_random_steps(Solver, N, 3)
+    errs = compare_state(got, E, H, TOL32, ("fp32", N, 3))
+    print("fp32 random material", N, 3, "errors", errs)
+
+
+class Float32Storage(maxwell.Problem):
+    """The oracle with its state rounded to float32 where the float32 mode
+    stores it (the E components after the E stage, before the H stage reads
+    them; the H components after the H stage), the solves exact: the error
+    that float32 storage alone leaves."""
+
+    def substep(self, sub, E, H, t):
+        r32 = lambda x: x.astype(np.float32).astype(np.float64)
+        fields = {"E1": E[0], "E2": E[1], "E3": E[2], "H1": H[0], "H2": H[1], "H3": H[2]}
+        t_mid = self.source_time(sub, t)
+        En = [r32(self.solve3(self.rhs_E(sub, fields, c, t_mid), "E", c, maxwell.MOD_AXIS[sub][c]))
+              for c in range(3)]
+        fields.update({"E1'": En[0], "E2'": En[1], "E3'": En[2]})
+        Hn = [r32(self.solve3(self.rhs_H(sub, fields, c), "H", c, None)) for c in range(3)]
+        return En, Hn
+
+
+@pytest.mark.parametrize("N", [4, 45])
+def test_full_steps_fp32_refine_degree4_rough(Solver, N):
+    """Degree 4 from a white-noise state on random material (sigma up to 20):
+    at N = 4 (dt = 1/8) the float32 storage of the state alone, with exact
+    solves, leaves up to 1.2e-4 on a strongly damped component, so 1e-5 per
+    component is out of reach of any float32-state method there.  The float32
+    mode rounds twice per stage (the increment's float32 solve and the stored
+    sum), both amplified through the step like the storage rounding: the
+    bound per component is 1e-5, or four times the storage-only model's
+    error where that is larger (max-abs: MAXABS_FACTOR32 times that)."""
+    prob, (E0, H0), got, E, H = _fp32_random_steps(Solver, N, 4)
+    S = Float32Storage(prob.N, prob.p, prob.eps, prob.mu, prob.sig, prob.dt, prob.source)
+    r32 = lambda L: [x.astype(np.float32).astype(np.float64) for x in L]
+    Es, Hs, _ = S.run(r32(E0), r32(H0), 0.01, 2)
+    ref = E + H
+    model = [rel_l2(a, b) for a, b in zip(Es + Hs, ref)]
+    tol = [max(TOL32, 4 * m) for m in model]
+    errs = [rel_l2(got[c], ref[c]) for c in range(6)]
+    emax = [max_abs_rel(got[c], ref[c]) for c in range(6)]
+    print("fp32 degree 4", N, "model", model, "errors", errs, "max-abs", emax)
+    assert all(e <= t for e, t in zip(errs, tol)), (errs, tol)
+    assert all(e <= MAXABS_FACTOR32 * t for e, t in zip(emax, tol)), (emax, tol)
 
 
 def test_mms16_manufactured_solution(Solver):
@@ -226,18 +290,26 @@ def _workload_pair(Solver, name, steps, precision="fp64"):
 
 
 def test_blob64_fp64(Solver):
-    got, E, H = _workload_pair(Solver, "blob64", 4)
+    got, E, H = _workload_pair(Solver, "blob64", 20)
     compare_state(got, E, H, TOL64, "blob64")
 
 
 def test_blob64_fp32_refine(Solver):
-    got, E, H = _workload_pair(Solver, "blob64", 4, "fp32_refine")
+    got, E, H = _workload_pair(Solver, "blob64", 20, "fp32_refine")
     compare_state(got, E, H, TOL32, "blob64 fp32")
 
 
+def test_shell128_p3_full_size_fp32(Solver):
+    """The benchmarked path: the 128^3 p=3 workload in the float32 mode at its
+    real size, two steps, every output, per component."""
+    got, E, H = _workload_pair(Solver, "shell128", 2, "fp32_refine")
+    errs = compare_state(got, E, H, TOL32, "shell128 fp32")
+    print("shell128 fp32 per component", errs)
+
+
 def test_shell128_p3_full_size_fp64(Solver):
-    """The 128^3 p=3 workload at its real size: one step, every output."""
-    got, E, H = _workload_pair(Solver, "shell128", 1)
+    """The 128^3 p=3 workload at its real size: three steps, every output."""
+    got, E, H = _workload_pair(Solver, "shell128", 3)
     compare_state(got, E, H, TOL64, "shell128")
 
 
@@ -298,7 +370,10 @@ def test_profiling_pass_equals_graph_steps(Solver, precision):
     assert outs[0][1] == outs[1][1]
     kinds = [L["kind"] for L in launches]
     assert kinds.count("rhs_E") == 2 and kinds.count("rhs_H") == 2
-    assert kinds.count("residual64") == (2 if precision == "fp32_refine" else 0)
+    assert kinds.count("residual64") == 0
+    # the float32 mode adds the old state in the last solves of each stage
+    nacc = sum(L["nacc"] for L in launches)
+    assert nacc == (12 if precision == "fp32_refine" else 0)
     assert all(L["ms"] > 0 for L in launches)
 
 
@@ -365,13 +440,9 @@ def test_local_time_step_steps(Solver, N, p):
 @pytest.mark.parametrize("precision,tol", [("fp64", TOL64), ("fp32_refine", TOL32)])
 def test_shell32_subrun_50_steps(Solver, precision, tol):
     """The 32^3 p=2 sub-run of the 256^3 shell workload (same voxel map):
-    all 50 steps of its dt, error of the electric and of the magnetic field
-    (relative L2 over its three components) against the float64 oracle.
-    The per-component errors are printed: with the x-directed dipole H1 is a
-    small component whose right-hand side is a difference of E terms, so its
-    own relative error follows E's float32 rounding scaled by |E| / |H1|."""
+    all 50 steps of its dt against the float64 oracle, per component (and
+    per field, printed)."""
     got, E, H = _workload_pair(Solver, "shell32", 50, precision)
-    comp = [rel_l2(got[c], (E + H)[c]) for c in range(6)]
     fields = {"E": rel_l2(got[:3], np.stack(E)), "H": rel_l2(got[3:], np.stack(H))}
+    comp = compare_state(got, E, H, tol, ("shell32", precision))
     print("shell32", precision, "per-field relative L2:", fields, "per component:", comp)
-    assert max(fields.values()) <= tol, fields
