@@ -205,6 +205,19 @@ int adi_mms_errors(adi_ctx* ctx, int q, double* out);
 int adi_project(adi_ctx* ctx, const double* vals_qp, int q, double t);
 
 /*
+ * adi_mms_errors for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same four errors from the same kernel, with the quadrature tables and
+ * the per-block partial sums in a fixed device array of the library (1 MiB
+ * per GPU, held until the process ends) instead of buffers allocated on
+ * first use.  ENOMEM if N q (2p + 4) + 8192 float64 values exceed it (never
+ * for N q <= 10240).  Call with the context's device current.  Every call on
+ * one GPU uses the same array: calls that overlap on one GPU (from other
+ * streams or threads) race.  Waits for the context's stream.
+ */
+int adi_mms_errors_noalloc(adi_ctx* ctx, int q, double* out);
+
+/*
  * Single hot-path stages on host buffers (float64 in and out), for testing
  * one step of the method against a reference.  Each runs the same kernels as
  * adi_step and synchronises.

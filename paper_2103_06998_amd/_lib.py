@@ -47,6 +47,7 @@ SIGNATURES = {
     "adi_mms_project": (_I, [_P, _I, ctypes.c_double]),
     "adi_mms_errors": (_I, [_P, _I, _D]),
     "adi_project": (_I, [_P, _D, _I, ctypes.c_double]),
+    "adi_mms_errors_noalloc": (_I, [_P, _I, _D]),
     "adi_profile_run": (_I, [_P, _I]),
     "adi_profile_read": (_I, [_P, _I, ctypes.POINTER(_I), ctypes.POINTER(_I),
                               ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_I),

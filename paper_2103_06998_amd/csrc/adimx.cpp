@@ -1428,4 +1428,34 @@ int adi_mms_errors(adi_ctx* c, int q, double* out) {
   return ADI_OK;
 }
 
+int adi_mms_errors_noalloc(adi_ctx* c, int q, double* out) {
+  if (!c || !out) return ADI_EINVAL;
+  if (q < 1 || q > 16) return fail(c, ADI_EINVAL, "quadrature points per element must be 1..16");
+  const int N = c->N, p = c->p;
+  const size_t ntab = size_t(N) * q * (2 + 2 * (p + 1));
+  const size_t part_off = (ntab + 31) / 32 * 32;  // partials 256-byte aligned
+  if ((part_off + size_t(mms::kMaxErrorBlocks) * 4) * 8 > mms::kNoAllocScratchBytes)
+    return fail(c, ADI_ENOMEM, "quadrature tables and partial sums exceed the fixed scratch");
+  if (!c->ws) return fail(c, ADI_ESTATE, "no state");
+  double* scr = nullptr;  // this GPU's copy of the library's fixed device array
+  HIPCHK(c, mms::noalloc_scratch(&scr));
+  std::vector<double> tab;
+  mms_host_tables(N, p, q, tab);
+  HIPCHK(c, hipMemcpyAsync(scr, tab.data(), ntab * 8, hipMemcpyHostToDevice, c->stream));
+  const mms::Tables tb = tables_at(scr, N, p, q);
+  double* partial = scr + part_off;
+  int nblk = 0;
+  HIPCHK(c, c->esz == 8
+                ? mms::launch_errors<double>(tb, static_cast<const double*>(c->B[0]), c->t,
+                                             partial, &nblk, c->stream)
+                : mms::launch_errors<float>(tb, static_cast<const float*>(c->B[0]), c->t,
+                                            partial, &nblk, c->stream));
+  std::vector<double> part(size_t(nblk) * 4);
+  HIPCHK(c, hipMemcpyAsync(part.data(), partial, part.size() * 8, hipMemcpyDeviceToHost,
+                           c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));  // also keeps `tab` alive until its copy is done
+  errors_from_partials(part, nblk, out);
+  return ADI_OK;
+}
+
 }  // extern "C"

@@ -8,6 +8,7 @@
 #include "mms_internal.h"
 
 #include <cmath>
+#include <mutex>
 
 namespace adimx {
 namespace mms {
@@ -162,7 +163,32 @@ int grid_for(size_t work) {
   return int(std::min<size_t>((work + 255) / 256, size_t(kMaxErrorBlocks)));
 }
 
+// The allocation-free error entry point's working memory: quadrature tables
+// and per-block partial sums.  Each GPU holds its own copy; host code uses
+// only the address hipGetSymbolAddress returns for the current device.
+__device__ __align__(256) double scratch[kNoAllocScratchBytes / sizeof(double)];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
 }  // namespace
+
+hipError_t noalloc_scratch(double** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
 
 hipError_t launch_exact(const Tables& tb, double t, double* vals, hipStream_t s) {
   const size_t Q = size_t(tb.N) * tb.q;

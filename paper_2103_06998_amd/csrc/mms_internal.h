@@ -11,6 +11,14 @@ namespace mms {
 // and derivatives bd[a*(p+1) + r]; coordinates x[a] and weights w[a].
 constexpr int kMaxErrorBlocks = 2048;
 
+// Size of the fixed device array behind adi_mms_errors_noalloc (one copy per
+// GPU, held until the process ends).
+constexpr size_t kNoAllocScratchBytes = size_t(1) << 20;
+
+// Device address of the current GPU's copy of that array (looked up with
+// hipGetSymbolAddress once per device, then cached).
+hipError_t noalloc_scratch(double** out);
+
 struct Tables {
   const double* x;
   const double* w;

@@ -206,6 +206,12 @@ class Solver:
         a = self._arr(vals_qp, 6 * Q ** 3)
         self._check(self.lib.adi_project(self.h, _lib.dptr(a), int(q), float(t)))
 
+    def mms_errors_noalloc(self, q: int = 0) -> dict:
+        """mms_errors through the entry point that allocates no device memory."""
+        out = np.empty(4)
+        self._check(self.lib.adi_mms_errors_noalloc(self.h, int(q or self.p + 3), _lib.dptr(out)))
+        return {"E_L2": out[0], "E_Hcurl": out[1], "H_L2": out[2], "H_Hcurl": out[3]}
+
     def mms_errors(self, q: int = 0) -> dict:
         """Absolute L2 and H(curl) errors of E and H against the manufactured
         solution at the current time."""

@@ -111,6 +111,27 @@ def test_network_host_validation(lib):
     assert lib.adi_step_closure(None, None, 1, ctypes.c_float(0.0)) == _lib.ADI_EINVAL
 
 
+def test_noalloc_errors_host_validation(lib):
+    """adi_mms_errors_noalloc checks its sizes against the fixed 1 MiB device
+    array on the host, before touching the device."""
+    out = np.zeros(4)
+    d = _lib.dptr
+    st, h = _ctx(lib, N=700, p=4)
+    assert st == _lib.ADI_OK
+    try:
+        # 700 * 16 * (2*4 + 4) + 8192 float64 values do not fit in 1 MiB
+        assert lib.adi_mms_errors_noalloc(h, 16, d(out)) == _lib.ADI_ENOMEM
+        assert b"scratch" in lib.adi_last_error(h)
+        assert lib.adi_mms_errors_noalloc(h, 0, d(out)) == _lib.ADI_EINVAL
+        assert lib.adi_mms_errors_noalloc(h, 17, d(out)) == _lib.ADI_EINVAL
+        # fits (700 * 1 * 12 + 8192), but no state yet
+        assert lib.adi_mms_errors_noalloc(h, 1, d(out)) == _lib.ADI_ESTATE
+        assert lib.adi_mms_errors_noalloc(h, 1, None) == _lib.ADI_EINVAL
+    finally:
+        lib.adi_destroy(h)
+    assert lib.adi_mms_errors_noalloc(None, 3, d(out)) == _lib.ADI_EINVAL
+
+
 def test_project_host_validation(lib):
     st, h = _ctx(lib)
     try:
