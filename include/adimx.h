@@ -10,18 +10,19 @@
  * with adi_bind_workspace (that workspace must outlive the context).
  *
  * Method (Paszynski, Los, Munoz-Matute, arXiv 2103.06998):
- *   domain (0,1)^3, N^3 uniform elements, degree-p B-splines of continuity
- *   C^{p-1} on open uniform knots, n = N + p coefficients per axis and field
- *   component; E and H each have three components (section "Alternating
- *   directions splitting for Maxwell equations").  One time step is two
+ *   domain (0,1)^3, Nx x Ny x Nz uniform elements, degree-p B-splines of
+ *   continuity C^{p-1} on open uniform knots, n_a = N_a + p coefficients
+ *   along axis a per field component; E and H each have three components
+ *   (section "Alternating directions splitting for Maxwell equations").  One time step is two
  *   substeps (eqs. scheme1a-scheme1d, discretised as discrete1-discrete4):
  *   a sum-factorised right-hand side, then three direction-wise banded
  *   (bandwidth 2p+1) line solves per component, with the material attached
  *   to test functions (section "Incorporating non-regular material data").
  *
  * Layout of every field array at this boundary: six components
- * [E1,E2,E3,H1,H2,H3], each n^3 float64 in [z][y][x] order with x fastest
- * (the paper's reordering of each right-hand side into N_x rows).
+ * [E1,E2,E3,H1,H2,H3], each D = nx ny nz float64 in [z][y][x] order with x
+ * fastest (the paper's reordering of each right-hand side into N_x rows of
+ * N_y N_z columns, section "Incorporating non-regular material data").
  */
 #ifndef ADIMX_H
 #define ADIMX_H
@@ -63,15 +64,21 @@ enum {
 };
 
 /*
- * Create a context for an N x N x N element patch of degree p (1 <= p <= 4,
- * N >= 1; only cubic patches nx = ny = nz are supported) on HIP stream
- * `hip_stream` (a hipStream_t, NULL = the null stream).  Nothing is
- * allocated on the device until adi_factor.  *out receives the handle.
+ * Create a context for a patch of nx x ny x nz elements (each >= 1; the
+ * element counts may differ per axis, each axis gets its own 1D matrices)
+ * of degree p (1 <= p <= 4) in precision mode `precision`, on HIP stream
+ * `hip_stream` (a hipStream_t, NULL = the null stream).  EINVAL for sizes
+ * out of range, including (nx+p)(ny+p)(nz+p) >= 2^31.  Nothing is allocated
+ * on the device until adi_factor.  *out receives the handle.  The learned
+ * closure calls need a cubic patch.
  */
 int adi_create(adi_ctx** out, int nx, int ny, int nz, int p, int precision, void* hip_stream);
 
-/* Number of coefficients per axis (N + p). */
+/* Number of coefficients along x (nx + p; along every axis of a cube). */
 int adi_ncoef(const adi_ctx* ctx);
+
+/* Coefficients per axis, n_out[a] = N_a + p for a = x, y, z. */
+int adi_dims(const adi_ctx* ctx, int* n_out);
 
 /*
  * Bytes of device memory the context needs once factored (fields, scratch,
@@ -83,7 +90,8 @@ size_t adi_workspace_bytes(const adi_ctx* ctx);
 int adi_bind_workspace(adi_ctx* ctx, void* dev_ptr, size_t bytes);
 
 /*
- * Material given as a voxel map (vx, vy, vz voxels, x fastest, float64):
+ * Material given as a voxel map (vx, vy, vz voxels, x fastest, float64)
+ * over the unit cube, independent of the element counts:
  * relative permittivity, relative permeability and the non-dimensional
  * conductivity sigma_nd = Z0 L sigma.  Material is attached to test
  * functions (eq. dupa1abcdefg and the text around it): with map_mode
@@ -96,7 +104,7 @@ int adi_bind_workspace(adi_ctx* ctx, void* dev_ptr, size_t bytes);
 int adi_set_material(adi_ctx* ctx, const double* eps_r, const double* mu_r,
                      const double* sigma_nd, int vx, int vy, int vz, int map_mode);
 
-/* Material given directly per degree of freedom (three n^3 arrays, x fastest). */
+/* Material given directly per degree of freedom (three D arrays, x fastest). */
 int adi_set_material_dof(adi_ctx* ctx, const double* eps, const double* mu, const double* sigma_nd);
 
 /*
@@ -119,13 +127,13 @@ int adi_factor(adi_ctx* ctx, double dt);
 int adi_set_source(adi_ctx* ctx, const double xs[3], int comp, double amp, double f0,
                    double t0, double width);
 
-/* Upload a state (6 n^3 float64, layout above) and set the time t. */
+/* Upload a state (6 D float64, layout above) and set the time t. */
 int adi_set_fields(adi_ctx* ctx, const double* EH, double t);
 
 /*
  * Local time step per test function (section "Incorporating non-regular
  * material data": like eps and mu, tau may be replaced by tau-hat for a test
- * function): tau holds n^3 values (layout as the fields, finite, >= 0) that
+ * function): tau holds D values (layout as the fields, finite, >= 0) that
  * replace dt in the row coefficients alpha, beta, gamma, delta of that
  * degree of freedom; the time levels (source time, time advance) stay those
  * of dt.  tau = NULL restores dt everywhere.  Takes effect at the next
@@ -143,7 +151,7 @@ int adi_step(adi_ctx* ctx, int nsteps);
 int adi_get_fields(adi_ctx* ctx, double* EH_out, double* t_out);
 
 /*
- * Device pointer of the current state (6 n^3 contiguous values of dtype
+ * Device pointer of the current state (6 D contiguous values of dtype
  * *dtype: 0 = float64, 1 = float32) for zero-copy access.  Valid until the
  * next adi_step / adi_set_fields / adi_destroy.
  */
@@ -193,10 +201,11 @@ int adi_mms_errors(adi_ctx* ctx, int q, double* out);
  * "Numerical code verification with manufactured solution": the initial
  * state is a projection of the given fields onto the spline space; the
  * problem statement of section "Alternating directions splitting for Maxwell
- * equations" takes E and H at t = 0 as data).  vals_qp holds 6 (N q)^3
- * float64 values, [component E1..E3,H1..H3][z][y][x], on the tensor grid of
- * the q-point Gauss-Legendre rule of every element (point e q + g of an axis
- * is Gauss point g of element e, x fastest); 1 <= q <= 16.  The state
+ * equations" takes E and H at t = 0 as data).  vals_qp holds
+ * 6 (Nx q)(Ny q)(Nz q) float64 values, [component E1..E3,H1..H3][z][y][x],
+ * on the tensor grid of the q-point Gauss-Legendre rule of every element
+ * (point e q + g of an axis is Gauss point g of element e, x fastest);
+ * 1 <= q <= 16.  The state
  * becomes, per component, the solution of (M (x) M (x) M) c = (f, B_r B_s B_t)
  * with the PEC-constrained coefficients zero, and the time t.  Copied before
  * the call returns.  ENONFINITE for a value that is not finite, ESTATE before
@@ -210,8 +219,8 @@ int adi_project(adi_ctx* ctx, const double* vals_qp, int q, double t);
  * the same four errors from the same kernel, with the quadrature tables and
  * the per-block partial sums in a fixed device array of the library (1 MiB
  * per GPU, held until the process ends) instead of buffers allocated on
- * first use.  ENOMEM if N q (2p + 4) + 8192 float64 values exceed it (never
- * for N q <= 10240).  Call with the context's device current.  Every call on
+ * first use.  ENOMEM if (Nx + Ny + Nz) q (2p + 4) + 8192 float64 values
+ * exceed it (never for (Nx + Ny + Nz) q <= 10240).  Call with the context's device current.  Every call on
  * one GPU uses the same array: calls that overlap on one GPU (from other
  * streams or threads) race.  Waits for the context's stream.
  */
@@ -225,9 +234,9 @@ int adi_mms_errors_noalloc(adi_ctx* ctx, int q, double* out);
  * adi_rhs: right-hand sides of one stage.  stage 0 = E (eqs. discrete1 /
  *   discrete3: in = [E1,E2,E3,H1,H2,H3], t = time at the start of the
  *   substep), stage 1 = H (eqs. discrete2 / discrete4: in = [H1,H2,H3,
- *   E_old1..3, E_new1..3]); sub = 1 or 2.  out receives 3 n^3 values with
+ *   E_old1..3, E_new1..3]); sub = 1 or 2.  out receives 3 D values with
  *   the constrained boundary rows zeroed.
- * adi_solve: the three 1D solves of one stage applied to 3 n^3 right-hand
+ * adi_solve: the three 1D solves of one stage applied to 3 D right-hand
  *   sides in place (E: modified axis first, then the other two; H: x, y, z).
  */
 int adi_rhs(adi_ctx* ctx, int stage, int sub, const double* in, double t, double* out);

@@ -147,14 +147,23 @@ def voxel_weights(N: int, p: int, V: int) -> np.ndarray:
     return W / W.sum(axis=1, keepdims=True)
 
 
-def average_material(N: int, p: int, eps_vox, mu_vox, sig_vox):
+def axis_counts(N):
+    """Elements per axis (Nx, Ny, Nz) of a patch given as N (cubic) or a triple."""
+    Ns = tuple(int(v) for v in np.broadcast_to(np.asarray(N), (3,)))
+    if min(Ns) < 1:
+        raise ValueError("need at least one element per axis")
+    return Ns
+
+
+def average_material(N, p: int, eps_vox, mu_vox, sig_vox):
     """Per-DOF (eps, mu, sigma) as the B-spline-weighted average of a voxel map:
     the material of test function B_r B_s B_t is the mean of the voxel values
     weighted by that function (a smoother alternative to Greville sampling of
     the test-function-wise material of the section on non-regular material).
-    Voxel arrays are (Vz, Vy, Vx)."""
+    Voxel arrays are (Vz, Vy, Vx); N is the element count, or one per axis."""
+    Nx, Ny, Nz = axis_counts(N)
     Vz, Vy, Vx = np.shape(eps_vox)
-    wx, wy, wz = voxel_weights(N, p, Vx), voxel_weights(N, p, Vy), voxel_weights(N, p, Vz)
+    wx, wy, wz = voxel_weights(Nx, p, Vx), voxel_weights(Ny, p, Vy), voxel_weights(Nz, p, Vz)
     def avg(m):
         m = np.asarray(m, float)                  # (Vz, Vy, Vx)
         m = np.einsum("ia,cba->cbi", wx, m)       # x
@@ -163,18 +172,18 @@ def average_material(N: int, p: int, eps_vox, mu_vox, sig_vox):
     return avg(eps_vox), avg(mu_vox), avg(sig_vox)
 
 
-def sample_material(N: int, p: int, eps_vox, mu_vox, sig_vox):
+def sample_material(N, p: int, eps_vox, mu_vox, sig_vox):
     """Per-DOF (eps, mu, sigma) by Greville sampling of a voxel map (R4).
 
     Voxel arrays are (Vz, Vy, Vx); DOF (i,j,k) takes the voxel that contains
-    (xi_i, xi_j, xi_k), voxel index min(floor(xi * V), V - 1) per axis.
+    (xi_i, xi_j, xi_k), voxel index min(floor(xi * V), V - 1) per axis.  N is
+    the element count, or one per axis.
     """
-    knots = bspline.open_uniform_knots(N, p)
-    xi = bspline.greville(knots, p)
+    xi = [bspline.greville(bspline.open_uniform_knots(Na, p), p) for Na in axis_counts(N)]
     Vz, Vy, Vx = np.shape(eps_vox)
-    ix = np.minimum(np.floor(xi * Vx).astype(int), Vx - 1)
-    iy = np.minimum(np.floor(xi * Vy).astype(int), Vy - 1)
-    iz = np.minimum(np.floor(xi * Vz).astype(int), Vz - 1)
+    ix = np.minimum(np.floor(xi[0] * Vx).astype(int), Vx - 1)
+    iy = np.minimum(np.floor(xi[1] * Vy).astype(int), Vy - 1)
+    iz = np.minimum(np.floor(xi[2] * Vz).astype(int), Vz - 1)
     sel = np.ix_(iz, iy, ix)
     return (np.asarray(eps_vox, float)[sel], np.asarray(mu_vox, float)[sel],
             np.asarray(sig_vox, float)[sel])
@@ -192,9 +201,12 @@ def coefficients(eps, mu, sig, dt):
 
 @dataclasses.dataclass
 class Problem:
-    """A patch of N^3 elements of degree p with per-DOF material and a step."""
+    """A patch of Nx x Ny x Nz elements of degree p (N an int for a cube, or
+    a triple) with per-DOF material and a step.  Each axis has its own 1D
+    matrices; the field arrays are (nz, ny, nx), n_a = N_a + p (the paper's
+    reordering of a right-hand side into N_x rows of N_y N_z columns)."""
 
-    N: int
+    N: object
     p: int
     eps: np.ndarray
     mu: np.ndarray
@@ -208,25 +220,35 @@ class Problem:
     local_dt: Optional[np.ndarray] = None
 
     def __post_init__(self):
-        self.n = self.N + self.p
-        shape = (self.n,) * 3
+        self.Ns = axis_counts(self.N)
+        self.ns = tuple(Na + self.p for Na in self.Ns)
+        self.cubic = len(set(self.Ns)) == 1
+        if self.cubic:
+            self.N, self.n = self.Ns[0], self.ns[0]
+        shape = self.shape = (self.ns[2], self.ns[1], self.ns[0])
         self.eps = np.broadcast_to(np.asarray(self.eps, float), shape).copy()
         self.mu = np.broadcast_to(np.asarray(self.mu, float), shape).copy()
         self.sig = np.broadcast_to(np.asarray(self.sig, float), shape).copy()
         if np.any(self.eps <= 0) or np.any(self.mu <= 0) or np.any(self.sig < 0):
             raise ValueError("need eps > 0, mu > 0, sigma >= 0")
-        self.M, self.S, self.A, self.B = gram.gram_matrices(self.N, self.p)
-        self.ops = {"M": self.M, "A": self.A, "B": self.B}
+        # per axis (x, y, z): {"M", "S", "A", "B"} of that axis's 1D space
+        self.axis_ops = []
+        for Na in self.Ns:
+            M, S, A, B = gram.gram_matrices(Na, self.p)
+            self.axis_ops.append({"M": M, "S": S, "A": A, "B": B})
+        self.M, self.S, self.A, self.B = (self.axis_ops[0][k] for k in "MSAB")
         tau = self.dt if self.local_dt is None else \
             np.broadcast_to(np.asarray(self.local_dt, float), shape).copy()
         self.coef = coefficients(self.eps, self.mu, self.sig, tau)
         self.coef["one"] = np.ones(shape)
-        self.knots = bspline.open_uniform_knots(self.N, self.p)
+        self.axis_knots = [bspline.open_uniform_knots(Na, self.p) for Na in self.Ns]
+        self.knots = self.axis_knots[0]
 
     # -- building blocks ---------------------------------------------------
     def apply(self, u: np.ndarray, ops: str) -> np.ndarray:
-        """(X (x) Y (x) Z) u for an operator string "XYZ"."""
-        X, Y, Z = (self.ops[o] for o in ops)
+        """(X (x) Y (x) Z) u for an operator string "XYZ" (each letter the 1D
+        matrix of its own axis)."""
+        X, Y, Z = (self.axis_ops[a][o] for a, o in enumerate(ops))
         return banded.apply3(u, X, Y, Z, self.p)
 
     def source_time(self, sub: int, t: float) -> float:
@@ -239,15 +261,13 @@ class Problem:
         """(J(t), V_rst) for component c: a g(t) B_r(xs) B_s(ys) B_t(zs) for
         the point dipole; a source object with its own ``rows`` method
         (e.g. ``SeparableSource``) computes the rows itself."""
-        out = np.zeros((self.n,) * 3)
+        out = np.zeros(self.shape)
         src = self.source
         if src is not None and hasattr(src, "rows"):
             return src.rows(self, c, t)
         if src is None or src.comp != c or src.amp == 0.0:
             return out
-        bx = bspline.basis(self.knots, self.p, [src.xs[0]])[0]
-        by = bspline.basis(self.knots, self.p, [src.xs[1]])[0]
-        bz = bspline.basis(self.knots, self.p, [src.xs[2]])[0]
+        bx, by, bz = (bspline.basis(self.axis_knots[a], self.p, [src.xs[a]])[0] for a in range(3))
         return src.amp * source_time(t, src) * np.einsum("k,j,i->kji", bz, by, bx)
 
     def solve3(self, R: np.ndarray, kind: str, c: int, mod_axis: Optional[int]) -> np.ndarray:
@@ -261,22 +281,23 @@ class Problem:
             [mod_axis] + [a for a in range(3) if a != mod_axis]
         u = R
         for a in order:
+            Ma = self.axis_ops[a]["M"]
             if a == mod_axis:
-                u = banded.solve_axis(u, _NP_AXIS[a], self.M, self.p, stiff=self.S,
+                u = banded.solve_axis(u, _NP_AXIS[a], Ma, self.p, stiff=self.axis_ops[a]["S"],
                                       alpha=self.coef["alpha"], dirichlet=a in dax)
             else:
-                u = banded.solve_axis(u, _NP_AXIS[a], self.M, self.p, dirichlet=a in dax)
+                u = banded.solve_axis(u, _NP_AXIS[a], Ma, self.p, dirichlet=a in dax)
         return u
 
     def rhs_E(self, sub: int, fields: dict, c: int, t_mid: float) -> np.ndarray:
-        R = np.zeros((self.n,) * 3)
+        R = np.zeros(self.shape)
         for coef, sign, f, ops in E_TERMS[sub][c]:
             R += sign * self.coef[coef] * self.apply(fields[f], ops)
         R -= self.coef["beta"] * self.source_rows(c, t_mid)
         return zero_boundary(R, dirichlet_axes("E", c))
 
     def rhs_H(self, sub: int, fields: dict, c: int) -> np.ndarray:
-        R = np.zeros((self.n,) * 3)
+        R = np.zeros(self.shape)
         for coef, sign, f, ops in H_TERMS[sub][c]:
             R += sign * self.coef[coef] * self.apply(fields[f], ops)
         return zero_boundary(R, dirichlet_axes("H", c))
@@ -338,16 +359,16 @@ class SeparableSource:
 
     def rows(self, prob: "Problem", c: int, t: float) -> np.ndarray:
         if c != self.comp:
-            return np.zeros((prob.n,) * 3)
-        x, w = bspline.gauss_points(prob.N, self.q)
-        V = bspline.basis(prob.knots, prob.p, x)          # (Q, n)
-        ix = (w * self.fx(x)) @ V
-        iy = (w * self.fy(x)) @ V
-        iz = (w * self.fz(x)) @ V
-        return float(self.j(t)) * np.einsum("k,j,i->kji", iz, iy, ix)
+            return np.zeros(prob.shape)
+        ints = []
+        for a, f in enumerate((self.fx, self.fy, self.fz)):
+            x, w = bspline.gauss_points(prob.Ns[a], self.q)
+            V = bspline.basis(prob.axis_knots[a], prob.p, x)   # (Q, n_a)
+            ints.append((w * f(x)) @ V)
+        return float(self.j(t)) * np.einsum("k,j,i->kji", ints[2], ints[1], ints[0])
 
 
-def problem_from_voxels(N: int, p: int, material, dt: float, source=None,
+def problem_from_voxels(N, p: int, material, dt: float, source=None,
                         mapping: str = "greville") -> Problem:
     """Problem with voxel material (sigma non-dimensional) mapped to the test
     functions by Greville sampling or by the B-spline-weighted average."""

@@ -77,26 +77,33 @@ def curl_u_A(x, y, z, t):
 
 
 class Quadrature:
-    """Tensor Gauss quadrature and basis tables for one N, p."""
+    """Tensor Gauss quadrature and basis tables for one N (an int, or one
+    element count per axis) and p: q points per element and axis."""
 
-    def __init__(self, N: int, p: int, q: int | None = None):
+    def __init__(self, N, p: int, q: int | None = None):
+        self.Ns = maxwell.axis_counts(N)
         self.N, self.p = N, p
         self.q = q if q is not None else p + 3
-        knots = bspline.open_uniform_knots(N, p)
-        self.x, self.w = bspline.gauss_points(N, self.q)
-        self.V = bspline.basis(knots, p, self.x)        # (Q, n)
-        self.D = bspline.basis_deriv(knots, p, self.x)  # (Q, n)
-        self.Z, self.Y, self.X = np.meshgrid(self.x, self.x, self.x, indexing="ij")
-        self.W = np.einsum("k,j,i->kji", self.w, self.w, self.w)
+        self.xs, self.ws, self.Vs, self.Ds = [], [], [], []
+        for Na in self.Ns:
+            knots = bspline.open_uniform_knots(Na, p)
+            x, w = bspline.gauss_points(Na, self.q)
+            self.xs.append(x)
+            self.ws.append(w)
+            self.Vs.append(bspline.basis(knots, p, x))        # (Q_a, n_a)
+            self.Ds.append(bspline.basis_deriv(knots, p, x))  # (Q_a, n_a)
+        self.x, self.w, self.V, self.D = self.xs[0], self.ws[0], self.Vs[0], self.Ds[0]
+        self.Z, self.Y, self.X = np.meshgrid(self.xs[2], self.xs[1], self.xs[0], indexing="ij")
+        self.W = np.einsum("k,j,i->kji", self.ws[2], self.ws[1], self.ws[0])
 
     def evaluate(self, c: np.ndarray, deriv_axis: int | None = None) -> np.ndarray:
         """Spline with coefficients c (nz,ny,nx) at all quadrature points.
 
         deriv_axis (0=x, 1=y, 2=z) selects a first derivative along that axis.
         """
-        T = [self.V, self.V, self.V]
+        T = list(self.Vs)
         if deriv_axis is not None:
-            T[deriv_axis] = self.D
+            T[deriv_axis] = self.Ds[deriv_axis]
         out = np.einsum("qi,kji->kjq", T[0], c)
         out = np.einsum("qj,kjr->kqr", T[1], out)
         out = np.einsum("qk,kjr->qjr", T[2], out)
@@ -112,19 +119,20 @@ def project(prob: maxwell.Problem, quad: Quadrature, values) -> tuple:
     Solves (M (x) M (x) M) c = (f, V) on the constrained space of each
     component (boundary rows identity, boundary right-hand side zero).
     """
-    WV = quad.V * quad.w[:, None]  # (Q, n)
+    WV = [V * w[:, None] for V, w in zip(quad.Vs, quad.ws)]  # (Q_a, n_a) per axis
     out = []
     for comp in range(6):
         f = values[comp]
-        r = np.einsum("qi,kjq->kji", WV, f)
-        r = np.einsum("qj,kqi->kji", WV, r)
-        r = np.einsum("qk,qji->kji", WV, r)
+        r = np.einsum("qi,kjq->kji", WV[0], f)
+        r = np.einsum("qj,kqi->kji", WV[1], r)
+        r = np.einsum("qk,qji->kji", WV[2], r)
         kind, c = ("E", comp) if comp < 3 else ("H", comp - 3)
         dax = maxwell.dirichlet_axes(kind, c)
         r = maxwell.zero_boundary(r, dax)
         u = r
         for a in range(3):
-            u = banded.solve_axis(u, maxwell._NP_AXIS[a], prob.M, prob.p, dirichlet=a in dax)
+            u = banded.solve_axis(u, maxwell._NP_AXIS[a], prob.axis_ops[a]["M"], prob.p,
+                                  dirichlet=a in dax)
         out.append(u)
     return out[0:3], out[3:6]
 

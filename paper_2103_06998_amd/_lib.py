@@ -27,6 +27,7 @@ _F = ctypes.POINTER(ctypes.c_float)
 SIGNATURES = {
     "adi_create": (_I, [ctypes.POINTER(_P), _I, _I, _I, _I, _I, _P]),
     "adi_ncoef": (_I, [_P]),
+    "adi_dims": (_I, [_P, ctypes.POINTER(_I)]),
     "adi_workspace_bytes": (ctypes.c_size_t, [_P]),
     "adi_bind_workspace": (_I, [_P, _P, ctypes.c_size_t]),
     "adi_set_material": (_I, [_P, _D, _D, _D, _I, _I, _I, _I]),

@@ -45,8 +45,11 @@ struct Region {
 }  // namespace
 
 struct adi_ctx {
-  int N = 0, p = 0, n = 0, prec = ADI_FP64;
-  size_t D = 0;            // n^3
+  int Ns[3] = {0, 0, 0};   // elements per axis (x, y, z)
+  int ns[3] = {0, 0, 0};   // coefficients per axis, N_a + p
+  int N = 0, n = 0;        // elements and coefficients along x (all axes of a cube)
+  int p = 0, prec = ADI_FP64;
+  size_t D = 0;            // nx ny nz
   size_t esz = 8;          // bytes per field element
   hipStream_t stream = nullptr;
   hipStream_t cap = nullptr;
@@ -73,14 +76,15 @@ struct adi_ctx {
   void* coefT[4] = {};      // alpha, beta, gamma, delta in the field type
   double* coef64[4] = {};   // float64 copies (refine mode), else alias of coefT
   void* gm1T = nullptr;     // gamma - 1 (refine mode: group coefficient of the E increments)
-  void* bandT = nullptr;    // [M,A,B,S][n][2p+1] in the field type
-  double* band64 = nullptr; // same in float64
+  void* bandT[3] = {};      // per axis: [M,A,B,S][n_a][2p+1] in the field type
+  double* band64[3] = {};   // same in float64
   void* zwT = nullptr;      // z weights [M,A,B,S][k][2p+1] in the field type
   double* zw64 = nullptr;   // same in float64
-  double* fb64 = nullptr;   // factor bands: Mdir, Sdir (n (2p+1) each)
-  void* shL[2] = {}, *shU[2] = {}, *shD[2] = {};  // shared factors: [0] free, [1] Dirichlet
-  void* spk[2] = {};        // partitioned-solve data of the shared factors (same variants)
-  bool spike_ok = false;    // spk holds valid data for the current factorisation
+  double* fb64[3] = {};     // per axis, factor bands: Mdir, Sdir (n_a (2p+1) each)
+  // shared factors per axis: [axis][0] free, [axis][1] Dirichlet
+  void* shL[3][2] = {}, *shU[3][2] = {}, *shD[3][2] = {};
+  void* spk[3][2] = {};     // partitioned-solve data of the shared factors (same variants)
+  bool spike_ok[3] = {};    // spk[axis] holds valid data for the current factorisation
   void* mL[6] = {}, *mU[6] = {}, *mD[6] = {};     // per-line factors, system (s-1)*3 + c
   double* minratio = nullptr;
   double* d_t = nullptr;
@@ -138,7 +142,7 @@ size_t layout(adi_ctx* c, unsigned char* base) {
     return ptr;
   };
   const size_t D = c->D, es = c->esz;
-  const int n = c->n, W = 2 * c->p + 1, P = c->p;
+  const int W = 2 * c->p + 1, P = c->p;
   // B0..B3 contiguous so that B0|B1 (the state) is one 6 D array
   unsigned char* b = take(4 * 3 * D * es);
   for (int i = 0; i < 4; ++i) c->B[i] = b ? b + size_t(i) * 3 * D * es : nullptr;
@@ -147,28 +151,33 @@ size_t layout(adi_ctx* c, unsigned char* base) {
     c->coef64[i] = c->refine() ? reinterpret_cast<double*>(take(D * 8))
                                : reinterpret_cast<double*>(c->coefT[i]);
   c->gm1T = c->refine() ? take(D * es) : nullptr;
-  c->bandT = take(size_t(4) * n * W * es);
-  c->band64 = reinterpret_cast<double*>(take(size_t(4) * n * W * 8));
-  c->zwT = take(size_t(4) * n * W * es);
-  c->zw64 = reinterpret_cast<double*>(take(size_t(4) * n * W * 8));
-  c->fb64 = reinterpret_cast<double*>(take(size_t(2) * n * W * 8));
-  for (int v = 0; v < 2; ++v) {
-    c->shL[v] = take(size_t(n) * P * es);
-    c->shU[v] = take(size_t(n) * P * es);
-    c->shD[v] = take(size_t(n) * es);
-  }
-  {
+  for (int ax = 0; ax < 3; ++ax) {
+    const int n = c->ns[ax];
+    c->bandT[ax] = take(size_t(4) * n * W * es);
+    c->band64[ax] = reinterpret_cast<double*>(take(size_t(4) * n * W * 8));
+    c->fb64[ax] = reinterpret_cast<double*>(take(size_t(2) * n * W * 8));
     const int q = 2 * P * (kSpikeS - 1);
-    for (int v = 0; v < 2; ++v) c->spk[v] = take((size_t(n) * (4 * P + 1) + size_t(q) * q) * es);
+    for (int v = 0; v < 2; ++v) {
+      c->shL[ax][v] = take(size_t(n) * P * es);
+      c->shU[ax][v] = take(size_t(n) * P * es);
+      c->shD[ax][v] = take(size_t(n) * es);
+      c->spk[ax][v] = take((size_t(n) * (4 * P + 1) + size_t(q) * q) * es);
+    }
   }
-  // per-line factors in blocks of 64 lines (the line count padded to 64)
-  const size_t nlpad = (size_t(n) * n + 63) / 64 * 64;
+  c->zwT = take(size_t(4) * c->ns[2] * W * es);
+  c->zw64 = reinterpret_cast<double*>(take(size_t(4) * c->ns[2] * W * 8));
+  // per-line factors of system s (its modified axis a: D / n_a lines of n_a
+  // rows) in blocks of 64 lines (the line count padded to 64)
+  size_t maxlines = 0;
   for (int s = 0; s < 6; ++s) {
+    const int n = c->ns[kModAxis[s / 3][s % 3]];
+    const size_t nlpad = (D / size_t(n) + 63) / 64 * 64;
+    maxlines = std::max(maxlines, D / size_t(n));
     c->mL[s] = take(size_t(P) * n * nlpad * es);
     c->mU[s] = take(size_t(P) * n * nlpad * es);
     c->mD[s] = take(size_t(n) * nlpad * es);
   }
-  c->minratio = reinterpret_cast<double*>(take(size_t(n) * n * 8));
+  c->minratio = reinterpret_cast<double*>(take(maxlines * 8));
   c->d_t = reinterpret_cast<double*>(take(8));
   return cur + 256;
 }
@@ -192,12 +201,13 @@ int upload(adi_ctx* c, void* dst, const std::vector<double>& src) {
   return ADI_OK;
 }
 
-// Output planes per RHS block: the grid is 3 ceil(n/32) ceil(n/8)
-// ceil(n/zchunk) blocks of 256 threads (one per tile and output component),
+// Output planes per RHS block: the grid is 3 ceil(nx/32) ceil(ny/8)
+// ceil(nz/zchunk) blocks of 256 threads (one per tile and output component),
 // about two resident per CU; pick the chunk (>= 8 planes, to bound the
 // 2p-plane halo) whose block count best fills whole rounds of 512 slots.
-int pick_zchunk(int n) {
-  const long xy = 3L * ((n + 31) / 32) * ((n + 7) / 8);
+int pick_zchunk(const int* ns) {
+  const int n = ns[2];
+  const long xy = 3L * ((ns[0] + 31) / 32) * ((ns[1] + 7) / 8);
   const long slots = 512;
   int best = n;
   double best_eff = -1.0;
@@ -261,10 +271,13 @@ RhsArgs<T> rhs_args(adi_ctx* c, const void* const* f, int nf, void* const* out, 
     a.coef[1] = c->coefT[1];  // beta
     a.coef[2] = c->coefT[0];  // alpha
   }
-  a.band = static_cast<const T*>(c->bandT);
+  a.bandx = static_cast<const T*>(c->bandT[0]);
+  a.bandy = static_cast<const T*>(c->bandT[1]);
   a.zw = static_cast<const T*>(c->zwT);
-  a.n = c->n;
-  a.zchunk = pick_zchunk(c->n);
+  a.nx = c->ns[0];
+  a.ny = c->ns[1];
+  a.nz = c->ns[2];
+  a.zchunk = pick_zchunk(c->ns);
   a.src = c->src;
   a.tnow = c->d_t;
   a.frac_dt = (sub == 1 ? 0.25 : 0.75) * c->dt;
@@ -287,13 +300,28 @@ SweepDesc desc_for(adi_ctx* c, int kindH, int sub, int comp_i, int axis, void* i
     d.modified = 1;
   } else {
     const int v = dirichlet(kindH, comp_i, axis) ? 1 : 0;
-    d.L = c->shL[v];
-    d.U = c->shU[v];
-    d.D = c->shD[v];
-    d.spk = c->spike_ok ? c->spk[v] : nullptr;
+    d.L = c->shL[axis][v];
+    d.U = c->shU[axis][v];
+    d.D = c->shD[axis][v];
+    d.spk = c->spike_ok[axis] ? c->spk[axis][v] : nullptr;
     d.modified = 0;
   }
   return d;
+}
+
+// Partitioned solves for a launch: every descriptor shared, with
+// partition data for its axis.
+int spike_for(const SweepArgs& a, int nd) {
+  for (int q = 0; q < nd; ++q)
+    if (a.d[q].modified || !a.d[q].spk) return 0;
+  return nd > 0 ? 1 : 0;
+}
+
+// Blocks of 64 lines a launch of these descriptors runs per descriptor.
+size_t line_blocks(const adi_ctx* c, const SweepDesc* d, int nd) {
+  size_t b = 0;
+  for (int q = 0; q < nd; ++q) b = std::max(b, (c->D / size_t(c->ns[d[q].axis]) + 63) / 64);
+  return b;
 }
 
 // Solve order of component c: modified axis first for E, x y z for H.
@@ -345,19 +373,19 @@ hipError_t enqueue_solves(adi_ctx* c, int kindH, int sub, void* buf, const void*
             (acc_base && r == 2) ? comp(const_cast<void*>(acc_base), ci, c) : nullptr;
         a.d[nd[xgroup]++] = desc_for(c, kindH, sub, ci, ax, in, in, acc);
       }
-      a.n = c->n;
-      a.nlines = c->n * c->n;
+      for (int k = 0; k < 3; ++k) a.dim[k] = c->ns[k];
       a.xaxis = xgroup;
       a.tick_t = nullptr;
-      int nmod = 0;
-      for (int q = 0; q < nd[xgroup]; ++q) nmod += a.d[q].modified;
-      a.spike = (c->spike_ok && nmod == 0) ? 1 : 0;
+      a.spike = spike_for(a, nd[xgroup]);
     }
     // x and y/z descriptors of one kind (all modified or all shared), with
     // at most 1024 blocks of 64 lines in all: one launch, x descriptors
     // first (no cross-stream fork and join, which cost 5-9 us per round);
     // larger rounds run better as two concurrent launches
-    const size_t blocks = size_t((c->n * c->n + 63) / 64) * size_t(nd[0] + nd[1]);
+    SweepDesc alld[6];
+    for (int q = 0; q < nd[1]; ++q) alld[q] = grp[1].d[q];
+    for (int q = 0; q < nd[0]; ++q) alld[nd[1] + q] = grp[0].d[q];
+    const size_t blocks = line_blocks(c, alld, nd[0] + nd[1]) * size_t(nd[0] + nd[1]);
     if (nd[0] > 0 && nd[1] > 0 && blocks <= 1024) {
       const int nmod0 = [&] { int m = 0; for (int q = 0; q < nd[0]; ++q) m += grp[0].d[q].modified; return m; }();
       const int nmod1 = [&] { int m = 0; for (int q = 0; q < nd[1]; ++q) m += grp[1].d[q].modified; return m; }();
@@ -366,7 +394,7 @@ hipError_t enqueue_solves(adi_ctx* c, int kindH, int sub, void* buf, const void*
         SweepArgs a = grp[1];
         for (int q = 0; q < nd[0]; ++q) a.d[nd[1] + q] = grp[0].d[q];
         a.xaxis = 2;
-        a.spike = (c->spike_ok && mall == 0) ? 1 : 0;
+        a.spike = spike_for(a, nall);
         const int nacc = (acc_base && r == 2) ? nall : 0;
         hipError_t e = timed(c, s, kKindSweepXYZ, nall, mall, nacc,
                              [&] { return launch_sweep<T>(c->p, nall, a, s); });
@@ -427,7 +455,8 @@ hipError_t enqueue_step_t(adi_ctx* c, hipStream_t s) {
       } else {
         RhsArgs<double> a = rhs_args<double>(c, f, 6, out, 0, sub);
         a.coef[0] = c->gm1T;  // gamma - 1: the mass part of P E folded in
-        a.band = c->band64;
+        a.bandx = c->band64[0];
+        a.bandy = c->band64[1];
         a.zw = c->zw64;
         e = timed(c, s, kKindRhsE, 3, 0, 0, [&] {
           return launch_rhs_inc(sub == 1 ? kStageEd1 : kStageEd2, c->p, a, s);
@@ -452,7 +481,8 @@ hipError_t enqueue_step_t(adi_ctx* c, hipStream_t s) {
       } else {
         // increments b - M H_old: the delta terms alone (H_old is not read)
         RhsArgs<double> a = rhs_args<double>(c, f, 9, out, 1, sub);
-        a.band = c->band64;
+        a.bandx = c->band64[0];
+        a.bandy = c->band64[1];
         a.zw = c->zw64;
         e = timed(c, s, kKindRhsH, 3, 0, 0, [&] {
           return launch_rhs_inc(sub == 1 ? kStageHd1 : kStageHd2, c->p, a, s);
@@ -468,10 +498,9 @@ hipError_t enqueue_step_t(adi_ctx* c, hipStream_t s) {
           void* io = comp(Hout, ci, c);
           w.d[ci] = desc_for(c, 1, sub, ci, ax, io, io, add ? comp(Hin, ci, c) : nullptr);
         }
-        w.n = c->n;
-        w.nlines = c->n * c->n;
+        for (int k = 0; k < 3; ++k) w.dim[k] = c->ns[k];
         w.xaxis = ax == 0;
-        w.spike = c->spike_ok ? 1 : 0;
+        w.spike = spike_for(w, 3);
         if (sub == 2 && ax == 2) {
           w.tick_t = c->d_t;
           w.tick_dt = c->dt;
@@ -551,13 +580,21 @@ extern "C" {
 int adi_create(adi_ctx** out, int nx, int ny, int nz, int p, int precision, void* hip_stream) {
   if (!out) return ADI_EINVAL;
   *out = nullptr;
-  if (nx < 1 || p < 1 || p > kMaxP || nx != ny || nx != nz) return ADI_EINVAL;
+  if (nx < 1 || ny < 1 || nz < 1 || p < 1 || p > kMaxP) return ADI_EINVAL;
   if (precision != ADI_FP64 && precision != ADI_FP32_REFINE) return ADI_EINVAL;
+  // coefficients per component below 2^31 (32-bit line and column indices)
+  const size_t D = size_t(nx + p) * size_t(ny + p) * size_t(nz + p);
+  if (D >= (size_t(1) << 31)) return ADI_EINVAL;
   adi_ctx* c = new adi_ctx();
+  const int Ns[3] = {nx, ny, nz};
+  for (int a = 0; a < 3; ++a) {
+    c->Ns[a] = Ns[a];
+    c->ns[a] = Ns[a] + p;
+  }
   c->N = nx;
   c->p = p;
   c->n = nx + p;
-  c->D = size_t(c->n) * c->n * c->n;
+  c->D = D;
   c->prec = precision;
   c->esz = precision == ADI_FP64 ? 8 : 4;
   c->stream = static_cast<hipStream_t>(hip_stream);
@@ -569,9 +606,19 @@ int adi_create(adi_ctx** out, int nx, int ny, int nz, int p, int precision, void
 
 int adi_ncoef(const adi_ctx* c) { return c ? c->n : ADI_EINVAL; }
 
+int adi_dims(const adi_ctx* c, int* n_out) {
+  if (!c || !n_out) return ADI_EINVAL;
+  for (int a = 0; a < 3; ++a) n_out[a] = c->ns[a];
+  return ADI_OK;
+}
+
 size_t adi_workspace_bytes(const adi_ctx* c) {
   if (!c) return 0;
   adi_ctx tmp;
+  for (int a = 0; a < 3; ++a) {
+    tmp.Ns[a] = c->Ns[a];
+    tmp.ns[a] = c->ns[a];
+  }
   tmp.N = c->N; tmp.p = c->p; tmp.n = c->n; tmp.D = c->D; tmp.prec = c->prec; tmp.esz = c->esz;
   return layout(&tmp, nullptr);
 }
@@ -624,16 +671,17 @@ int adi_set_material(adi_ctx* c, const double* eps_r, const double* mu_r, const 
   if (map_mode == ADI_MAP_BSPLINE_AVG) {
     // DOF (i,j,k) takes the voxel values averaged with the weights of its
     // test function B_i B_j B_k, one axis at a time (x, then y, then z)
-    const int n = c->n;
-    const std::vector<double> wx = voxel_weights(c->N, c->p, vx), wy = voxel_weights(c->N, c->p, vy),
-                              wz = voxel_weights(c->N, c->p, vz);
+    const int nx = c->ns[0], ny = c->ns[1], nz = c->ns[2];
+    const std::vector<double> wx = voxel_weights(c->Ns[0], c->p, vx),
+                              wy = voxel_weights(c->Ns[1], c->p, vy),
+                              wz = voxel_weights(c->Ns[2], c->p, vz);
     auto avg = [&](const double* m, std::vector<double>& out) {
-      std::vector<double> a(size_t(vz) * vy * n, 0.0), b(size_t(vz) * n * n, 0.0);
+      std::vector<double> a(size_t(vz) * vy * nx, 0.0), b(size_t(vz) * ny * nx, 0.0);
       for (int k = 0; k < vz; ++k)
         for (int j = 0; j < vy; ++j) {
           const double* row = m + (size_t(k) * vy + j) * vx;
-          double* o = a.data() + (size_t(k) * vy + j) * n;
-          for (int i = 0; i < n; ++i) {
+          double* o = a.data() + (size_t(k) * vy + j) * nx;
+          for (int i = 0; i < nx; ++i) {
             const double* w = wx.data() + size_t(i) * vx;
             double s = 0.0;
             for (int v = 0; v < vx; ++v) s += w[v] * row[v];
@@ -641,23 +689,24 @@ int adi_set_material(adi_ctx* c, const double* eps_r, const double* mu_r, const 
           }
         }
       for (int k = 0; k < vz; ++k)
-        for (int jj = 0; jj < n; ++jj) {
+        for (int jj = 0; jj < ny; ++jj) {
           const double* w = wy.data() + size_t(jj) * vy;
-          double* o = b.data() + (size_t(k) * n + jj) * n;
+          double* o = b.data() + (size_t(k) * ny + jj) * nx;
           for (int v = 0; v < vy; ++v) {
             if (w[v] == 0.0) continue;
-            const double* src = a.data() + (size_t(k) * vy + v) * n;
-            for (int i = 0; i < n; ++i) o[i] += w[v] * src[i];
+            const double* src = a.data() + (size_t(k) * vy + v) * nx;
+            for (int i = 0; i < nx; ++i) o[i] += w[v] * src[i];
           }
         }
       out.assign(c->D, 0.0);
-      for (int kk = 0; kk < n; ++kk) {
+      const size_t plane = size_t(nx) * ny;
+      for (int kk = 0; kk < nz; ++kk) {
         const double* w = wz.data() + size_t(kk) * vz;
-        double* o = out.data() + size_t(kk) * n * n;
+        double* o = out.data() + size_t(kk) * plane;
         for (int v = 0; v < vz; ++v) {
           if (w[v] == 0.0) continue;
-          const double* src = b.data() + size_t(v) * n * n;
-          for (size_t q = 0; q < size_t(n) * n; ++q) o[q] += w[v] * src[q];
+          const double* src = b.data() + size_t(v) * plane;
+          for (size_t q = 0; q < plane; ++q) o[q] += w[v] * src[q];
         }
       }
     };
@@ -669,23 +718,23 @@ int adi_set_material(adi_ctx* c, const double* eps_r, const double* mu_r, const 
     return ADI_OK;
   }
   // Greville sampling: DOF (i,j,k) takes the voxel containing (xi_i, xi_j, xi_k).
-  const std::vector<double> xi = greville(c->N, c->p);
-  const int n = c->n;
   auto vox = [](double x, int V) { return std::min(int(std::floor(x * V)), V - 1); };
-  std::vector<int> ix(n), iy(n), iz(n);
-  for (int i = 0; i < n; ++i) {
-    ix[i] = vox(xi[i], vx);
-    iy[i] = vox(xi[i], vy);
-    iz[i] = vox(xi[i], vz);
+  const int V3[3] = {vx, vy, vz};
+  std::vector<int> idx[3];
+  for (int ax = 0; ax < 3; ++ax) {
+    const std::vector<double> xi = greville(c->Ns[ax], c->p);
+    idx[ax].resize(c->ns[ax]);
+    for (int i = 0; i < c->ns[ax]; ++i) idx[ax][i] = vox(xi[i], V3[ax]);
   }
   c->eps.resize(c->D);
   c->mu.resize(c->D);
   c->sig.resize(c->D);
-  for (int k = 0; k < n; ++k)
-    for (int j = 0; j < n; ++j)
-      for (int i = 0; i < n; ++i) {
-        const size_t o = i + size_t(n) * (j + size_t(n) * k);
-        const size_t v = ix[i] + size_t(vx) * (iy[j] + size_t(vy) * iz[k]);
+  const int nx = c->ns[0], ny = c->ns[1], nz = c->ns[2];
+  for (int k = 0; k < nz; ++k)
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i) {
+        const size_t o = i + size_t(nx) * (j + size_t(ny) * k);
+        const size_t v = idx[0][i] + size_t(vx) * (idx[1][j] + size_t(vy) * idx[2][k]);
         c->eps[o] = eps_r[v];
         c->mu[o] = mu_r[v];
         c->sig[o] = sigma_nd[v];
@@ -726,13 +775,13 @@ int adi_set_source(adi_ctx* c, const double xs[3], int comp_i, double amp, doubl
     s.width = width;
     double vals[kMaxP + 1];
     int first;
-    basis_at(c->N, c->p, xs[0], &first, vals);
+    basis_at(c->Ns[0], c->p, xs[0], &first, vals);
     s.first[0] = first;
     for (int r = 0; r <= c->p; ++r) s.bx[r] = vals[r];
-    basis_at(c->N, c->p, xs[1], &first, vals);
+    basis_at(c->Ns[1], c->p, xs[1], &first, vals);
     s.first[1] = first;
     for (int r = 0; r <= c->p; ++r) s.by[r] = vals[r];
-    basis_at(c->N, c->p, xs[2], &first, vals);
+    basis_at(c->Ns[2], c->p, xs[2], &first, vals);
     s.first[2] = first;
     for (int r = 0; r <= c->p; ++r) s.bz[r] = vals[r];
   }
@@ -748,65 +797,80 @@ int adi_factor(adi_ctx* c, double dt) {
   if (!std::isfinite(dt) || dt < 0.0) return fail(c, ADI_EINVAL, "dt must be finite and >= 0");
   int st = ensure_workspace(c);
   if (st != ADI_OK) return st;
-  const int n = c->n, p = c->p, W = 2 * p + 1;
+  const int p = c->p, W = 2 * p + 1;
   const size_t D = c->D;
   c->dt = dt;
   c->cl_mat_valid = false;
 
-  // 1D operators (float64, exact Gauss quadrature)
-  Gram1D g = build_gram(c->N, p);
-  std::vector<double> ops(size_t(4) * n * W);
-  std::copy(g.M.begin(), g.M.end(), ops.begin());
-  std::copy(g.A.begin(), g.A.end(), ops.begin() + size_t(n) * W);
-  std::copy(g.B.begin(), g.B.end(), ops.begin() + size_t(2) * n * W);
-  std::copy(g.S.begin(), g.S.end(), ops.begin() + size_t(3) * n * W);
-  if ((st = upload(c, c->bandT, ops)) != ADI_OK) return st;
-  HIPCHK(c, hipMemcpy(c->band64, ops.data(), ops.size() * 8, hipMemcpyHostToDevice));
-  // z weights: input plane k contributes Z[k-p+q][k] to output plane k-p+q
-  std::vector<double> zw(size_t(4) * n * W, 0.0);
-  for (int op = 0; op < 4; ++op)
-    for (int k = 0; k < n; ++k)
-      for (int q = 0; q < W; ++q) {
-        const int t = k - p + q;
-        if (t < 0 || t >= n) continue;
-        zw[(size_t(op) * n + k) * W + q] = ops[(size_t(op) * n + t) * W + (k - t + p)];
-      }
-  if ((st = upload(c, c->zwT, zw)) != ADI_OK) return st;
-  HIPCHK(c, hipMemcpy(c->zw64, zw.data(), zw.size() * 8, hipMemcpyHostToDevice));
-
-  // shared factors of M (free) and M with Dirichlet rows/columns
-  for (int v = 0; v < 2; ++v) {
-    std::vector<double> band = g.M;
-    if (v) apply_dirichlet(band, n, p);
-    std::vector<double> L, U, Dinv;
-    const double r = band_lu(band, n, p, L, U, Dinv);
-    if (!(r > 1e-14)) return fail(c, ADI_ESINGULAR, "singular mass matrix factor");
-    for (int i = 0; i < n; ++i)  // pre-scale the upper factor: D * U
-      for (int k = 0; k < p; ++k) U[size_t(i) * p + k] *= Dinv[i];
-    if ((st = upload(c, c->shL[v], L)) != ADI_OK) return st;
-    if ((st = upload(c, c->shU[v], U)) != ADI_OK) return st;
-    if ((st = upload(c, c->shD[v], Dinv)) != ADI_OK) return st;
-  }
-  // partitioned-solve data of the same matrices (long lines only); any
-  // failed self-check keeps the one-lane-per-line solve
-  c->spike_ok = false;
-  if (n >= kSpikeMinN && n <= kSpikeMaxN) {
-    bool ok = true;
-    std::vector<double> pack[2];
-    for (int v = 0; v < 2 && ok; ++v) {
+  // per axis: 1D operators (float64, exact Gauss quadrature), shared factors
+  // of M (free) and M with Dirichlet rows/columns, their partitioned-solve
+  // data (long lines only; any failed self-check keeps the one-lane-per-line
+  // solve) and the bands the per-line factors are built from
+  Gram1D gz;
+  for (int ax = 0; ax < 3; ++ax) {
+    const int n = c->ns[ax];
+    Gram1D g = build_gram(c->Ns[ax], p);
+    std::vector<double> ops(size_t(4) * n * W);
+    std::copy(g.M.begin(), g.M.end(), ops.begin());
+    std::copy(g.A.begin(), g.A.end(), ops.begin() + size_t(n) * W);
+    std::copy(g.B.begin(), g.B.end(), ops.begin() + size_t(2) * n * W);
+    std::copy(g.S.begin(), g.S.end(), ops.begin() + size_t(3) * n * W);
+    if ((st = upload(c, c->bandT[ax], ops)) != ADI_OK) return st;
+    HIPCHK(c, hipMemcpy(c->band64[ax], ops.data(), ops.size() * 8, hipMemcpyHostToDevice));
+    if (ax == 2) {
+      // z weights: input plane k contributes Z[k-p+q][k] to output plane k-p+q
+      std::vector<double> zw(size_t(4) * n * W, 0.0);
+      for (int op = 0; op < 4; ++op)
+        for (int k = 0; k < n; ++k)
+          for (int q = 0; q < W; ++q) {
+            const int t = k - p + q;
+            if (t < 0 || t >= n) continue;
+            zw[(size_t(op) * n + k) * W + q] = ops[(size_t(op) * n + t) * W + (k - t + p)];
+          }
+      if ((st = upload(c, c->zwT, zw)) != ADI_OK) return st;
+      HIPCHK(c, hipMemcpy(c->zw64, zw.data(), zw.size() * 8, hipMemcpyHostToDevice));
+    }
+    for (int v = 0; v < 2; ++v) {
       std::vector<double> band = g.M;
       if (v) apply_dirichlet(band, n, p);
-      SpikeData sd;
-      ok = spike_prepare(band, n, p, kSpikeS, sd);
-      if (!ok) break;
-      for (const std::vector<double>* part : {&sd.L, &sd.DU, &sd.D, &sd.V, &sd.W, &sd.R})
-        pack[v].insert(pack[v].end(), part->begin(), part->end());
+      std::vector<double> L, U, Dinv;
+      const double r = band_lu(band, n, p, L, U, Dinv);
+      if (!(r > 1e-14)) return fail(c, ADI_ESINGULAR, "singular mass matrix factor");
+      for (int i = 0; i < n; ++i)  // pre-scale the upper factor: D * U
+        for (int k = 0; k < p; ++k) U[size_t(i) * p + k] *= Dinv[i];
+      if ((st = upload(c, c->shL[ax][v], L)) != ADI_OK) return st;
+      if ((st = upload(c, c->shU[ax][v], U)) != ADI_OK) return st;
+      if ((st = upload(c, c->shD[ax][v], Dinv)) != ADI_OK) return st;
     }
-    if (ok) {
-      for (int v = 0; v < 2; ++v)
-        if ((st = upload(c, c->spk[v], pack[v])) != ADI_OK) return st;
-      c->spike_ok = true;
+    c->spike_ok[ax] = false;
+    if (n >= kSpikeMinN && n <= kSpikeMaxN) {
+      bool ok = true;
+      std::vector<double> pack[2];
+      for (int v = 0; v < 2 && ok; ++v) {
+        std::vector<double> band = g.M;
+        if (v) apply_dirichlet(band, n, p);
+        SpikeData sd;
+        ok = spike_prepare(band, n, p, kSpikeS, sd);
+        if (!ok) break;
+        for (const std::vector<double>* part : {&sd.L, &sd.DU, &sd.D, &sd.V, &sd.W, &sd.R})
+          pack[v].insert(pack[v].end(), part->begin(), part->end());
+      }
+      if (ok) {
+        for (int v = 0; v < 2; ++v)
+          if ((st = upload(c, c->spk[ax][v], pack[v])) != ADI_OK) return st;
+        c->spike_ok[ax] = true;
+      }
     }
+    // bands of the material-modified systems along this axis (always
+    // Dirichlet: the modified axis of E_c is never axis c)
+    std::vector<double> fb(size_t(2) * n * W);
+    std::vector<double> Mb = g.M, Sb = g.S;
+    apply_dirichlet(Mb, n, p);
+    apply_dirichlet(Sb, n, p);
+    for (int b : {0, n - 1}) Sb[size_t(b) * W + p] = 0.0;  // identity rows carry no alpha S
+    std::copy(Mb.begin(), Mb.end(), fb.begin());
+    std::copy(Sb.begin(), Sb.end(), fb.begin() + size_t(n) * W);
+    HIPCHK(c, hipMemcpy(c->fb64[ax], fb.data(), fb.size() * 8, hipMemcpyHostToDevice));
   }
 
   // per-row coefficients (material attached to test functions), with the
@@ -833,26 +897,15 @@ int adi_factor(adi_ctx* c, double dt) {
   }
   if (c->refine() && (st = upload(c, c->gm1T, co[4])) != ADI_OK) return st;
 
-  // per-line factors of the modified systems (always Dirichlet: the modified
-  // axis of E_c is never axis c)
-  std::vector<double> fb(size_t(2) * n * W);
-  {
-    std::vector<double> Mb = g.M, Sb = g.S;
-    apply_dirichlet(Mb, n, p);
-    apply_dirichlet(Sb, n, p);
-    for (int b : {0, n - 1}) Sb[size_t(b) * W + p] = 0.0;  // identity rows carry no alpha S
-    std::copy(Mb.begin(), Mb.end(), fb.begin());
-    std::copy(Sb.begin(), Sb.end(), fb.begin() + size_t(n) * W);
-  }
-  HIPCHK(c, hipMemcpy(c->fb64, fb.data(), fb.size() * 8, hipMemcpyHostToDevice));
+  // per-line factors of the modified systems
   double worst = 1e300;
-  std::vector<double> ratios(size_t(n) * n);
   for (int sub = 1; sub <= 2; ++sub)
     for (int ci = 0; ci < 3; ++ci) {
       const int s = (sub - 1) * 3 + ci;
+      const int ax = kModAxis[sub - 1][ci], n = c->ns[ax];
       FactorArgs f{};
-      f.Mb = c->fb64;
-      f.Sb = c->fb64 + size_t(n) * W;
+      f.Mb = c->fb64[ax];
+      f.Sb = c->fb64[ax] + size_t(n) * W;
       f.alpha = c->coef64[0];
       if (c->refine()) {
         f.L32 = static_cast<float*>(c->mL[s]);
@@ -865,8 +918,11 @@ int adi_factor(adi_ctx* c, double dt) {
       }
       f.minratio = c->minratio;
       f.n = n;
-      f.nlines = n * n;
-      f.axis = kModAxis[sub - 1][ci];
+      f.nlines = int(D / size_t(n));
+      f.axis = ax;
+      f.nx = c->ns[0];
+      f.ny = c->ns[1];
+      std::vector<double> ratios(size_t(f.nlines));
       HIPCHK(c, launch_factor(p, f, c->cap));
       HIPCHK(c, hipMemcpyAsync(ratios.data(), c->minratio, ratios.size() * 8,
                                hipMemcpyDeviceToHost, c->cap));
@@ -1085,6 +1141,9 @@ namespace {
 constexpr int kClosureBlocks = 1024;
 
 int closure_ready(adi_ctx* c) {
+  // the network's features index the coefficient grid as a cube
+  if (c->ns[0] != c->ns[1] || c->ns[0] != c->ns[2])
+    return fail(c, ADI_EINVAL, "the learned closure needs a cubic patch (nx = ny = nz)");
   if (!c->factored) return fail(c, ADI_ESTATE, "adi_factor first");
   const size_t D = c->D;
   if (!c->cl_prev) {
@@ -1150,7 +1209,8 @@ extern "C" {
 
 int adi_copy_state(adi_ctx* dst, const adi_ctx* src) {
   if (!dst || !src) return ADI_EINVAL;
-  if (dst->n != src->n) return fail(dst, ADI_EINVAL, "grids differ");
+  if (dst->ns[0] != src->ns[0] || dst->ns[1] != src->ns[1] || dst->ns[2] != src->ns[2])
+    return fail(dst, ADI_EINVAL, "grids differ");
   if (!src->ws) return fail(dst, ADI_ESTATE, "source has no state");
   if (!dst->ws) {
     int st = ensure_workspace(dst);
@@ -1190,7 +1250,8 @@ int adi_closure_features(adi_ctx* c, float* x_dev, float* scale_dev) {
 
 int adi_closure_target(adi_ctx* fine, adi_ctx* coarse, const float* scale_dev, float* t_dev) {
   if (!fine || !coarse || !scale_dev || !t_dev) return ADI_EINVAL;
-  if (fine->n != coarse->n || !fine->ws || !coarse->ws)
+  if (fine->ns[0] != coarse->ns[0] || fine->ns[1] != coarse->ns[1] ||
+      fine->ns[2] != coarse->ns[2] || !fine->ws || !coarse->ws)
     return fail(coarse, ADI_EINVAL, "grids differ or no state");
   if (fine->esz != coarse->esz) return fail(coarse, ADI_EINVAL, "precisions differ");
   if (fine->stream != coarse->stream) HIPCHK(coarse, hipStreamSynchronize(fine->stream));
@@ -1207,6 +1268,8 @@ int adi_closure_target(adi_ctx* fine, adi_ctx* coarse, const float* scale_dev, f
 
 int adi_closure_apply(adi_ctx* c, const float* y_dev, const float* scale_dev) {
   if (!c || !y_dev || !scale_dev) return ADI_EINVAL;
+  if (c->ns[0] != c->ns[1] || c->ns[0] != c->ns[2])
+    return fail(c, ADI_EINVAL, "the learned closure needs a cubic patch (nx = ny = nz)");
   if (!c->ws) return fail(c, ADI_ESTATE, "no state");
   HIPCHK(c, enqueue_apply(c, y_dev, scale_dev, nullptr));
   return ADI_OK;
@@ -1256,45 +1319,61 @@ int adi_closure_rejected(adi_ctx* c, int* count) {
 // ------------------------------------------------ manufactured solution
 namespace {
 
-// Gauss tables of the q-point rule on every element of one axis (the patch
-// is a cube): coordinates x[Q], weights w[Q], then the p + 1 basis values
-// bv[Q][p+1] and derivatives bd[Q][p+1] of each point's element, Q = N q.
-void mms_host_tables(int N, int p, int q, std::vector<double>& tab) {
-  const int Q = N * q;
+// Gauss tables of the q-point rule on every element, axis after axis
+// (x, y, z): for axis a with Q_a = N_a q points, coordinates x[Q_a],
+// weights w[Q_a], then the p + 1 basis values bv[Q_a][p+1] and derivatives
+// bd[Q_a][p+1] of each point's element.
+size_t mms_table_size(const int* Ns, int p, int q) {
+  return size_t(Ns[0] + Ns[1] + Ns[2]) * q * (2 + 2 * (p + 1));
+}
+
+void mms_host_tables(const int* Ns, int p, int q, std::vector<double>& tab) {
   std::vector<double> gx, gw;
   gauss_legendre(q, gx, gw);
-  const std::vector<double> t = open_knots(N, p);
-  tab.assign(size_t(Q) * (2 + 2 * (p + 1)), 0.0);
-  double* X = tab.data();
-  double* Wt = X + Q;
-  double* BV = Wt + Q;
-  double* BD = BV + size_t(Q) * (p + 1);
+  tab.assign(mms_table_size(Ns, p, q), 0.0);
+  double* base = tab.data();
   std::vector<double> v(p + 1), d(p + 1);
-  for (int e = 0; e < N; ++e)
-    for (int g = 0; g < q; ++g) {
-      const int a = e * q + g;
-      X[a] = (e + 0.5 * (gx[g] + 1.0)) / N;
-      Wt[a] = 0.5 * gw[g] / N;
-      basis_on_span(t, p, e + p, X[a], v.data(), d.data());
-      for (int r = 0; r <= p; ++r) {
-        BV[size_t(a) * (p + 1) + r] = v[r];
-        BD[size_t(a) * (p + 1) + r] = d[r];
+  for (int ax = 0; ax < 3; ++ax) {
+    const int N = Ns[ax], Q = N * q;
+    const std::vector<double> t = open_knots(N, p);
+    double* X = base;
+    double* Wt = X + Q;
+    double* BV = Wt + Q;
+    double* BD = BV + size_t(Q) * (p + 1);
+    for (int e = 0; e < N; ++e)
+      for (int g = 0; g < q; ++g) {
+        const int a = e * q + g;
+        X[a] = (e + 0.5 * (gx[g] + 1.0)) / N;
+        Wt[a] = 0.5 * gw[g] / N;
+        basis_on_span(t, p, e + p, X[a], v.data(), d.data());
+        for (int r = 0; r <= p; ++r) {
+          BV[size_t(a) * (p + 1) + r] = v[r];
+          BD[size_t(a) * (p + 1) + r] = d[r];
+        }
       }
-    }
+    base += size_t(Q) * (2 + 2 * (p + 1));
+  }
 }
 
 // The device tables of mms_host_tables at `base`.
-mms::Tables tables_at(const double* base, int N, int p, int q) {
-  const int Q = N * q;
+mms::Tables tables_at(const double* base, const int* Ns, int p, int q) {
   mms::Tables tb{};
-  tb.x = base;
-  tb.w = base + Q;
-  tb.bv = base + 2 * Q;
-  tb.bd = base + 2 * Q + size_t(Q) * (p + 1);
-  tb.N = N;
+  for (int ax = 0; ax < 3; ++ax) {
+    const int Q = Ns[ax] * q;
+    tb.x[ax] = base;
+    tb.w[ax] = base + Q;
+    tb.bv[ax] = base + 2 * Q;
+    tb.bd[ax] = base + 2 * Q + size_t(Q) * (p + 1);
+    tb.N[ax] = Ns[ax];
+    base += size_t(Q) * (2 + 2 * (p + 1));
+  }
   tb.p = p;
   tb.q = q;
   return tb;
+}
+
+size_t quad_points(const adi_ctx* c, int q) {
+  return size_t(c->Ns[0]) * q * size_t(c->Ns[1]) * q * size_t(c->Ns[2]) * q;
 }
 
 // Tables on the device, and the buffers of the projection and errors
@@ -1302,9 +1381,8 @@ mms::Tables tables_at(const double* base, int N, int p, int q) {
 int mms_ready(adi_ctx* c, int q) {
   if (q < 1 || q > 16) return fail(c, ADI_EINVAL, "quadrature points per element must be 1..16");
   if (c->mms_q == q) return ADI_OK;
-  const int N = c->N, p = c->p, Q = N * q;
   std::vector<double> tab;
-  mms_host_tables(N, p, q, tab);
+  mms_host_tables(c->Ns, c->p, q, tab);
   if (c->mms_tab) hipFree(c->mms_tab);
   if (c->mms_vals) hipFree(c->mms_vals);
   c->mms_tab = nullptr;
@@ -1312,14 +1390,14 @@ int mms_ready(adi_ctx* c, int q) {
   c->mms_q = 0;
   HIPCHK(c, hipMalloc(reinterpret_cast<void**>(&c->mms_tab), tab.size() * 8));
   HIPCHK(c, hipMemcpy(c->mms_tab, tab.data(), tab.size() * 8, hipMemcpyHostToDevice));
-  HIPCHK(c, hipMalloc(reinterpret_cast<void**>(&c->mms_vals), 6 * size_t(Q) * Q * Q * 8));
+  HIPCHK(c, hipMalloc(reinterpret_cast<void**>(&c->mms_vals), 6 * quad_points(c, q) * 8));
   if (!c->mms_part)
     HIPCHK(c, hipMalloc(reinterpret_cast<void**>(&c->mms_part), mms::kMaxErrorBlocks * 4 * 8));
   c->mms_q = q;
   return ADI_OK;
 }
 
-mms::Tables mms_tables(const adi_ctx* c) { return tables_at(c->mms_tab, c->N, c->p, c->mms_q); }
+mms::Tables mms_tables(const adi_ctx* c) { return tables_at(c->mms_tab, c->Ns, c->p, c->mms_q); }
 
 // Sum the per-block partial sums of the error kernel (in block order) into
 // out: ||E_h - E||, its H(curl) norm, the same for H.
@@ -1345,16 +1423,15 @@ hipError_t enqueue_mass_solves(adi_ctx* c, int kindH, void* buf, hipStream_t s) 
       d.axis = ax;
       d.in = io;
       d.out = io;
-      d.L = c->shL[v];
-      d.U = c->shU[v];
-      d.D = c->shD[v];
-      d.spk = c->spike_ok ? c->spk[v] : nullptr;
+      d.L = c->shL[ax][v];
+      d.U = c->shU[ax][v];
+      d.D = c->shD[ax][v];
+      d.spk = c->spike_ok[ax] ? c->spk[ax][v] : nullptr;
       d.modified = 0;
     }
-    w.n = c->n;
-    w.nlines = c->n * c->n;
+    for (int k = 0; k < 3; ++k) w.dim[k] = c->ns[k];
     w.xaxis = ax == 0;
-    w.spike = c->spike_ok ? 1 : 0;
+    w.spike = spike_for(w, 3);
     hipError_t e = launch_sweep<T>(c->p, 3, w, s);
     if (e != hipSuccess) return e;
   }
@@ -1401,7 +1478,7 @@ int adi_project(adi_ctx* c, const double* vals_qp, int q, double t) {
   if (!c->factored) return fail(c, ADI_ESTATE, "adi_factor first");
   int st = mms_ready(c, q);
   if (st != ADI_OK) return st;
-  const size_t Q = size_t(c->N) * q, count = 6 * Q * Q * Q;
+  const size_t count = 6 * quad_points(c, q);
   if (!finite_all(vals_qp, count)) return fail(c, ADI_ENONFINITE, "value not finite");
   HIPCHK(c, hipStreamSynchronize(c->stream));
   HIPCHK(c, hipMemcpy(c->mms_vals, vals_qp, count * 8, hipMemcpyHostToDevice));
@@ -1431,8 +1508,7 @@ int adi_mms_errors(adi_ctx* c, int q, double* out) {
 int adi_mms_errors_noalloc(adi_ctx* c, int q, double* out) {
   if (!c || !out) return ADI_EINVAL;
   if (q < 1 || q > 16) return fail(c, ADI_EINVAL, "quadrature points per element must be 1..16");
-  const int N = c->N, p = c->p;
-  const size_t ntab = size_t(N) * q * (2 + 2 * (p + 1));
+  const size_t ntab = mms_table_size(c->Ns, c->p, q);
   const size_t part_off = (ntab + 31) / 32 * 32;  // partials 256-byte aligned
   if ((part_off + size_t(mms::kMaxErrorBlocks) * 4) * 8 > mms::kNoAllocScratchBytes)
     return fail(c, ADI_ENOMEM, "quadrature tables and partial sums exceed the fixed scratch");
@@ -1440,9 +1516,9 @@ int adi_mms_errors_noalloc(adi_ctx* c, int q, double* out) {
   double* scr = nullptr;  // this GPU's copy of the library's fixed device array
   HIPCHK(c, mms::noalloc_scratch(&scr));
   std::vector<double> tab;
-  mms_host_tables(N, p, q, tab);
+  mms_host_tables(c->Ns, c->p, q, tab);
   HIPCHK(c, hipMemcpyAsync(scr, tab.data(), ntab * 8, hipMemcpyHostToDevice, c->stream));
-  const mms::Tables tb = tables_at(scr, N, p, q);
+  const mms::Tables tb = tables_at(scr, c->Ns, c->p, q);
   double* partial = scr + part_off;
   int nblk = 0;
   HIPCHK(c, c->esz == 8

@@ -79,10 +79,11 @@ struct RhsArgs {
   const void* coef[3];    // per-row coefficients, in the kernel's coefficient type:
                           // E: gamma, beta, alpha (increments: gamma - 1, beta,
                           // alpha); H: delta
-  const T* band;          // [op][r][2p+1], op 0 = M, 1 = A, 2 = B, 3 = S
-  const T* zw;            // [op][k][2p+1]: weight of input plane k on output plane
-                          // k - p + q (band entry Z[k-p+q][k], zero outside)
-  int n;
+  const T* bandx;         // x axis: [op][r][2p+1], op 0 = M, 1 = A, 2 = B, 3 = S
+  const T* bandy;         // y axis, same layout
+  const T* zw;            // z axis: [op][k][2p+1]: weight of input plane k on output
+                          // plane k - p + q (band entry Z[k-p+q][k], zero outside)
+  int nx, ny, nz;         // coefficients per axis
   int zchunk;             // output planes per block
   SourceArgs src;
   const double* tnow;     // device time at the start of the step
@@ -105,8 +106,9 @@ struct SweepDesc {
 
 struct SweepArgs {
   SweepDesc d[3];         // blockIdx.y selects the descriptor
-  int n;
-  int nlines;
+  int dim[3];             // coefficients per axis (nx, ny, nz); a descriptor's
+                          // lines have dim[axis] rows, and there are
+                          // nx ny nz / dim[axis] of them
   int xaxis;              // 0: y/z lines, 1: x lines (transposing kernel),
                           // 2: both, descriptors of x lines first
   int spike;              // 1: shared-factor lines solved in kSpikeS segments each
@@ -115,13 +117,14 @@ struct SweepArgs {
 };
 
 struct FactorArgs {
-  const double* Mb;       // band of the base matrix (Dirichlet rows applied)
+  const double* Mb;       // band of the base matrix of the axis (Dirichlet rows applied)
   const double* Sb;       // band of the stiffness matrix (Dirichlet rows/cols zero)
-  const double* alpha;    // per-DOF coefficient (n^3, x fastest)
+  const double* alpha;    // per-DOF coefficient (nx ny nz, x fastest)
   double* L64; double* U64; double* D64;   // per-line factors (float64): L, D*U, D
   float* L32; float* U32; float* D32;      // float32 copies (refine mode) or null
   double* minratio;       // per line: min |U_rr| / |A_rr|
-  int n, nlines, axis;
+  int n, nlines, axis;    // rows per line (dim[axis]), lines, axis
+  int nx, ny;             // coefficients along x and y (line strides)
 };
 
 // Launchers (kernels.hip).  All enqueue on `stream` and return hipError_t.

@@ -176,7 +176,8 @@ size_t rhs_lds_bytes(int zchunk) {
 // coefficient type.
 template <typename TI, typename TC, typename TO, typename TK, int P, int STAGE>
 __global__ __launch_bounds__(kRhsThreads) void rhs_kernel(RhsArgs<TC> a,
-                                                          const TC* __restrict__ band,
+                                                          const TC* __restrict__ bandx,
+                                                          const TC* __restrict__ bandy,
                                                           const TC* __restrict__ zw) {
   constexpr int W = 2 * P + 1, HX = kTX + 2 * P, HY = kTY + 2 * P;
   constexpr int NT = StageInfo<STAGE>::NT, NG = StageInfo<STAGE>::NG;
@@ -194,8 +195,8 @@ __global__ __launch_bounds__(kRhsThreads) void rhs_kernel(RhsArgs<TC> a,
   TC* sYB = sG + 2 * GSZ;                // y band rows [op][yy][d] of the tile
   TC* sZW = sYB + 4 * kTY * W;           // z weights [plane - kbeg][op][q]
 
-  const int n = a.n;
-  const size_t plane = size_t(n) * n;
+  const int nx = a.nx, ny = a.ny, nz = a.nz;
+  const size_t plane = size_t(nx) * ny;
   const int tid = threadIdx.x;
   const int wave = tid / 64, lane = tid % 64;
   // Work item of this block.  Workgroups are dealt to the 8 XCDs (each with
@@ -221,7 +222,7 @@ __global__ __launch_bounds__(kRhsThreads) void rhs_kernel(RhsArgs<TC> a,
   const int tx = tid % kTX, ty = tid / kTX;
   const int i0 = bx * kTX, j0 = by * kTY;
   const int t0 = bz * a.zchunk;
-  const int t1 = min(n, t0 + a.zchunk);
+  const int t1 = min(nz, t0 + a.zchunk);
   const int i = i0 + tx, j = j0 + ty;
 
   // x band rows of this thread's output column (registers)
@@ -229,18 +230,18 @@ __global__ __launch_bounds__(kRhsThreads) void rhs_kernel(RhsArgs<TC> a,
 #pragma unroll
   for (int op = 0; op < 4; ++op)
 #pragma unroll
-    for (int d = 0; d < W; ++d) xb[op][d] = (i < n) ? band[(size_t(op) * n + i) * W + d] : TC(0);
+    for (int d = 0; d < W; ++d) xb[op][d] = (i < nx) ? bandx[(size_t(op) * nx + i) * W + d] : TC(0);
 
   // y band rows of the tile and z weights of the chunk's input planes (read
   // by every lane: LDS broadcasts instead of scalar loads in the plane loop)
-  const int kbeg = max(t0 - P, 0), kend = min(t1 + P, n);  // input planes to read
+  const int kbeg = max(t0 - P, 0), kend = min(t1 + P, nz);  // input planes to read
   for (int idx = tid; idx < 4 * kTY * W; idx += kRhsThreads) {
     const int op = idx / (kTY * W), rem = idx % (kTY * W), yy = rem / W, d = rem % W;
-    sYB[idx] = band[(size_t(op) * n + min(j0 + yy, n - 1)) * W + d];
+    sYB[idx] = bandy[(size_t(op) * ny + min(j0 + yy, ny - 1)) * W + d];
   }
   for (int idx = tid; idx < (kend - kbeg) * 4 * W; idx += kRhsThreads) {
     const int kk = idx / (4 * W), rem = idx % (4 * W), op = rem / W, q = rem % W;
-    sZW[idx] = zw[(size_t(op) * n + kbeg + kk) * W + q];
+    sZW[idx] = zw[(size_t(op) * nz + kbeg + kk) * W + q];
   }
 
   // This wave's field slot (its one or two y operators) and this lane's
@@ -258,22 +259,22 @@ __global__ __launch_bounds__(kRhsThreads) void rhs_kernel(RhsArgs<TC> a,
   const int pr0 = CT.spair[comp][slot][0], pr1 = CT.spair[comp][slot][1];
   const int yop0 = CT.pyop[comp][pr0], yop1 = CT.pyop[comp][pr1];
   // Addresses are a block-uniform row or plane pointer plus a 32-bit lane
-  // offset (n^2 < 2^31), which keeps one offset register per lane.
+  // offset (nx ny < 2^31), which keeps one offset register per lane.
   const TI* fsrc = static_cast<const TI*>(a.f[CT.field[comp][slot]]);
-  const unsigned loff = on ? unsigned(min(max(i0 - P + lane, 0), n - 1)) : 0u;
+  const unsigned loff = on ? unsigned(min(max(i0 - P + lane, 0), nx - 1)) : 0u;
   const size_t pstride = on ? plane : 0;
   int rows[HY];
 #pragma unroll
-  for (int m = 0; m < HY; ++m) rows[m] = on ? min(max(j0 - P + m, 0), n - 1) * n : 0;
+  for (int m = 0; m < HY; ++m) rows[m] = on ? min(max(j0 - P + m, 0), ny - 1) * nx : 0;
   auto load_plane = [&](int k, TI (&v)[HY]) {
     const TI* pp = fsrc + pstride * size_t(min(k, kend - 1));
 #pragma unroll
     for (int m = 0; m < HY; ++m) v[m] = (pp + rows[m])[loff];
   };
   // per-row coefficients of output plane te (clamped; used only when written)
-  const unsigned colo = unsigned(min(i, n - 1)) + unsigned(n) * unsigned(min(j, n - 1));
+  const unsigned colo = unsigned(min(i, nx - 1)) + unsigned(nx) * unsigned(min(j, ny - 1));
   auto load_cf = [&](int te, TC (&c)[NCF]) {
-    const size_t po = plane * size_t(min(max(te, 0), n - 1));
+    const size_t po = plane * size_t(min(max(te, 0), nz - 1));
 #pragma unroll
     for (int q = 0; q < NCF; ++q) c[q] = TC((static_cast<const TK*>(a.coef[q]) + po)[colo]);
   };
@@ -300,10 +301,10 @@ __global__ __launch_bounds__(kRhsThreads) void rhs_kernel(RhsArgs<TC> a,
 
   // write the complete output plane te (acc[.][0]) of this thread's column
   auto emit = [&](int te, const TC (&cf)[NCF]) {
-    const unsigned o = unsigned(i) + unsigned(n) * unsigned(j);
+    const unsigned o = unsigned(i) + unsigned(nx) * unsigned(j);
     const size_t po = plane * size_t(te);
-    const bool bi = (i == 0 || i == n - 1), bj = (j == 0 || j == n - 1),
-               bk = (te == 0 || te == n - 1);
+    const bool bi = (i == 0 || i == nx - 1), bj = (j == 0 || j == ny - 1),
+               bk = (te == 0 || te == nz - 1);
     if (kE) {
       const TC g = cf[0], b = cf[kE ? 1 : 0], al = cf[kE ? 2 : 0];
       TC v = g * acc[0][0] + b * acc[1][0] + al * acc[2 % NG][0];
@@ -329,7 +330,7 @@ __global__ __launch_bounds__(kRhsThreads) void rhs_kernel(RhsArgs<TC> a,
       acc[g][W - 1] = TC(0);
     }
   };
-  const bool inplane = i < n && j < n;
+  const bool inplane = i < nx && j < ny;
 
   // Input plane k (kbeg <= k < kend) is held in ring slot (k - kbeg) & 1 and
   // its y-pass result in LDS buffer (k - kbeg) & 1; the loop is unrolled by
@@ -477,19 +478,25 @@ __device__ __forceinline__ void sweep_body(const SweepArgs& a) {
   constexpr int kRA = kRR > 0 ? kRR : 1;  // register array extent
   extern __shared__ __align__(16) unsigned char smem[];
   T* buf = reinterpret_cast<T*>(smem);
-  const int n = a.n, nl = a.nlines, lane = threadIdx.x;
-  T* sfac = buf + size_t(sweep_buf_rows(n, XAX, kRR)) * PIT;  // shared: L[n*P], DU[n*P], D[n]
   const SweepDesc& ds = a.d[blockIdx.y];
+  const int nx = a.dim[0];
+  const size_t nxy = size_t(nx) * a.dim[1];
+  const int n = a.dim[ds.axis];                                   // rows per line
+  const int nl = int(nxy * size_t(a.dim[2]) / size_t(n));         // lines
+  const int lane = threadIdx.x;
   const int l0 = blockIdx.x * 64, l = l0 + lane;
+  if (l0 >= nl) return;  // the grid covers the descriptor with the most lines
+  T* sfac = buf + size_t(sweep_buf_rows(n, XAX, kRR)) * PIT;  // shared: L[n*P], DU[n*P], D[n]
   const bool act = l < nl;
   const int nll = min(64, nl - l0);  // lines in this tile
   const T* __restrict__ in = static_cast<const T*>(ds.in);
   T* __restrict__ out = static_cast<T*>(ds.out);
   const T* __restrict__ accp = static_cast<const T*>(ds.acc);
-  const size_t n2 = size_t(n) * n;
   const int lc = act ? l : 0;
-  const size_t lbase = (ds.axis == 1) ? size_t(lc % n) + size_t(lc / n) * n2 : size_t(lc);
-  const size_t rstride = (ds.axis == 1) ? size_t(n) : n2;
+  // y lines: line (i, k) starts at i + k nx ny, stride nx; z lines: line
+  // i + j nx starts there, stride nx ny
+  const size_t lbase = (ds.axis == 1) ? size_t(lc % nx) + size_t(lc / nx) * nxy : size_t(lc);
+  const size_t rstride = (ds.axis == 1) ? size_t(nx) : nxy;
   const int nreg = min(n, kRR);
 
   if (!MOD) {
@@ -857,10 +864,14 @@ __device__ __forceinline__ void spike_body(const SweepArgs& a) {
   constexpr int S = kSpikeS, Q = 2 * P * (S - 1);
   extern __shared__ __align__(16) unsigned char smem[];
   T* sf = reinterpret_cast<T*>(smem);
-  const int n = a.n, nl = a.nlines;
+  const SweepDesc& ds = a.d[blockIdx.y];
+  const int nx = a.dim[0];
+  const size_t nxy = size_t(nx) * a.dim[1];
+  const int n = a.dim[ds.axis];                                   // rows per line
+  const int nl = int(nxy * size_t(a.dim[2]) / size_t(n));         // lines
+  if (int(blockIdx.x) * 64 >= nl) return;  // block-uniform: before any barrier
   const int nf = n * (4 * P + 1) + Q * Q;
   T* gex = sf + nf;  // [Q][64] boundary values of g
-  const SweepDesc& ds = a.d[blockIdx.y];
   const int tid = threadIdx.x, seg = tid >> 6, lane = tid & 63;
   const T* sL = sf;
   const T* sDU = sf + n * P;
@@ -875,17 +886,16 @@ __device__ __forceinline__ void spike_body(const SweepArgs& a) {
   const int l = blockIdx.x * 64 + lane;
   const bool act = l < nl;
   const int lc = act ? l : 0;
-  const size_t n2 = size_t(n) * n;
   size_t lbase, rstride;
   if (XAX) {
     lbase = size_t(lc) * n;
     rstride = 1;
   } else if (ds.axis == 1) {
-    lbase = size_t(lc % n) + size_t(lc / n) * n2;
-    rstride = n;
+    lbase = size_t(lc % nx) + size_t(lc / nx) * nxy;
+    rstride = nx;
   } else {
     lbase = size_t(lc);
-    rstride = n2;
+    rstride = nxy;
   }
   const int b0 = (seg * n) / S, b1 = ((seg + 1) * n) / S, m = b1 - b0;  // m <= MR
 
@@ -1096,12 +1106,12 @@ __global__ __launch_bounds__(64) void factor_kernel(FactorArgs a) {
   constexpr int W = 2 * P + 1;
   const int l = blockIdx.x * 64 + threadIdx.x;
   if (l >= a.nlines) return;
-  const int n = a.n, nl = a.nlines;
-  const size_t n2 = size_t(n) * n;
+  const int n = a.n;
+  const size_t nxy = size_t(a.nx) * a.ny;
   size_t lbase, rstride;
   if (a.axis == 0) { lbase = size_t(l) * n; rstride = 1; }
-  else if (a.axis == 1) { lbase = size_t(l % n) + size_t(l / n) * n2; rstride = n; }
-  else { lbase = l; rstride = n2; }
+  else if (a.axis == 1) { lbase = size_t(l % a.nx) + size_t(l / a.nx) * nxy; rstride = a.nx; }
+  else { lbase = l; rstride = nxy; }
 
   double up[P + 1][P + 1];  // up[m][c] = U_{i-m, i-m+c}
 #pragma unroll
@@ -1184,9 +1194,8 @@ hipError_t launch_rhs_t(const RhsArgs<TC>& a, hipStream_t s) {
   const size_t lds = rhs_lds_bytes<TC, P, STAGE>(a.zchunk);
   hipError_t e = set_lds(k, lds);
   if (e != hipSuccess) return e;
-  const int n = a.n;
-  dim3 grid(3 * ((n + kTX - 1) / kTX), (n + kTY - 1) / kTY, (n + a.zchunk - 1) / a.zchunk);
-  hipLaunchKernelGGL(k, grid, dim3(kRhsThreads), lds, s, a, a.band, a.zw);
+  dim3 grid(3 * ((a.nx + kTX - 1) / kTX), (a.ny + kTY - 1) / kTY, (a.nz + a.zchunk - 1) / a.zchunk);
+  hipLaunchKernelGGL(k, grid, dim3(kRhsThreads), lds, s, a, a.bandx, a.bandy, a.zw);
   return hipGetLastError();
 }
 
@@ -1217,10 +1226,29 @@ size_t sweep_lds(int n) {
   return (size_t(sweep_buf_rows(n, XAX, SweepRegRows<T, MOD>::value)) * sweep_pitch(XAX) +
           (MOD ? 0 : size_t(n) * (2 * P + 1))) * sizeof(T);
 }
+
+// Longest line and largest line count over the descriptors of a launch: the
+// LDS is sized for the longest line, the grid for the most lines (blocks
+// past a descriptor's lines return at once).
+struct LaunchShape {
+  int nmax = 0, lines = 0;
+};
+inline LaunchShape launch_shape(int ndesc, const SweepArgs& a) {
+  LaunchShape r;
+  const size_t D = size_t(a.dim[0]) * a.dim[1] * a.dim[2];
+  for (int i = 0; i < ndesc; ++i) {
+    const int n = a.dim[a.d[i].axis];
+    r.nmax = std::max(r.nmax, n);
+    r.lines = std::max(r.lines, int(D / size_t(n)));
+  }
+  return r;
+}
+
 template <typename T, int P, bool XAX, bool MOD>
 hipError_t launch_sweep_k(int ndesc, const SweepArgs& a, hipStream_t s) {
-  const size_t lds = sweep_lds<T, P, XAX, MOD>(a.n);
-  dim3 grid((a.nlines + 63) / 64, ndesc);
+  const LaunchShape sh = launch_shape(ndesc, a);
+  const size_t lds = sweep_lds<T, P, XAX, MOD>(sh.nmax);
+  dim3 grid((sh.lines + 63) / 64, ndesc);
   auto k = sweep_kernel<T, P, XAX, MOD>;
   hipError_t e = set_lds(k, lds);
   if (e != hipSuccess) return e;
@@ -1229,8 +1257,10 @@ hipError_t launch_sweep_k(int ndesc, const SweepArgs& a, hipStream_t s) {
 }
 template <typename T, int P, bool MOD>
 hipError_t launch_sweep_mixed(int ndesc, const SweepArgs& a, hipStream_t s) {
-  const size_t lds = std::max(sweep_lds<T, P, true, MOD>(a.n), sweep_lds<T, P, false, MOD>(a.n));
-  dim3 grid((a.nlines + 63) / 64, ndesc);
+  const LaunchShape sh = launch_shape(ndesc, a);
+  const size_t lds =
+      std::max(sweep_lds<T, P, true, MOD>(sh.nmax), sweep_lds<T, P, false, MOD>(sh.nmax));
+  dim3 grid((sh.lines + 63) / 64, ndesc);
   auto k = sweep_mixed_kernel<T, P, MOD>;
   hipError_t e = set_lds(k, lds);
   if (e != hipSuccess) return e;
@@ -1241,9 +1271,10 @@ hipError_t launch_sweep_mixed(int ndesc, const SweepArgs& a, hipStream_t s) {
 template <typename T, int P, bool XAX, int MR>
 hipError_t launch_spike_k(int ndesc, const SweepArgs& a, hipStream_t s) {
   constexpr int Q = 2 * P * (kSpikeS - 1);
-  const size_t lds = (size_t(a.n) * (4 * P + 1) + Q * Q + size_t(Q) * 64 +
+  const LaunchShape sh = launch_shape(ndesc, a);
+  const size_t lds = (size_t(sh.nmax) * (4 * P + 1) + Q * Q + size_t(Q) * 64 +
                       (XAX ? size_t(kSpikeS) * 8 * 65 : 0)) * sizeof(T);
-  dim3 grid((a.nlines + 63) / 64, ndesc);
+  dim3 grid((sh.lines + 63) / 64, ndesc);
   auto k = spike_kernel<T, P, XAX, MR>;
   hipError_t e = set_lds(k, lds);
   if (e != hipSuccess) return e;
@@ -1254,9 +1285,10 @@ hipError_t launch_spike_k(int ndesc, const SweepArgs& a, hipStream_t s) {
 template <typename T, int P, int MR>
 hipError_t launch_spike_mixed_k(int ndesc, const SweepArgs& a, hipStream_t s) {
   constexpr int Q = 2 * P * (kSpikeS - 1);
-  const size_t lds = (size_t(a.n) * (4 * P + 1) + Q * Q + size_t(Q) * 64 +
+  const LaunchShape sh = launch_shape(ndesc, a);
+  const size_t lds = (size_t(sh.nmax) * (4 * P + 1) + Q * Q + size_t(Q) * 64 +
                       size_t(kSpikeS) * 8 * 65) * sizeof(T);
-  dim3 grid((a.nlines + 63) / 64, ndesc);
+  dim3 grid((sh.lines + 63) / 64, ndesc);
   auto k = spike_mixed_kernel<T, P, MR>;
   hipError_t e = set_lds(k, lds);
   if (e != hipSuccess) return e;
@@ -1266,8 +1298,8 @@ hipError_t launch_spike_mixed_k(int ndesc, const SweepArgs& a, hipStream_t s) {
 // xaxis: 0 = y/z lines, 1 = x lines, 2 = both (descriptor axis per block)
 template <typename T, int P>
 hipError_t launch_spike_x(int xaxis, int ndesc, const SweepArgs& a, hipStream_t s) {
-  // register rows per segment: ceil(n / kSpikeS)
-  const int m = (a.n + kSpikeS - 1) / kSpikeS;
+  // register rows per segment: ceil(n / kSpikeS) of the longest line
+  const int m = (launch_shape(ndesc, a).nmax + kSpikeS - 1) / kSpikeS;
   if (m <= 40) {
     if (xaxis == 2) return launch_spike_mixed_k<T, P, 40>(ndesc, a, s);
     return xaxis ? launch_spike_k<T, P, true, 40>(ndesc, a, s)
@@ -1288,9 +1320,10 @@ hipError_t launch_sweep_p(int ndesc, const SweepArgs& a, hipStream_t s) {
   for (int i = 1; i < ndesc; ++i)
     if ((a.d[i].modified != 0) != mod) return hipErrorInvalidValue;
   if (a.spike && !mod) {
-    if (a.n < kSpikeMinN || a.n > kSpikeMaxN) return hipErrorInvalidValue;
-    for (int i = 0; i < ndesc; ++i)
-      if (!a.d[i].spk) return hipErrorInvalidValue;
+    for (int i = 0; i < ndesc; ++i) {
+      const int n = a.dim[a.d[i].axis];
+      if (!a.d[i].spk || n < kSpikeMinN || n > kSpikeMaxN) return hipErrorInvalidValue;
+    }
     return launch_spike_x<T, P>(a.xaxis, ndesc, a, s);
   }
   if (a.xaxis == 2)

@@ -37,13 +37,13 @@ __device__ void exact(double x, double y, double z, double t, double* e, double*
 }
 
 __global__ void exact_kernel(Tables tb, double t, double* vals) {
-  const int Q = tb.N * tb.q;
-  const size_t Q3 = size_t(Q) * Q * Q;
+  const int Qx = tb.N[0] * tb.q, Qy = tb.N[1] * tb.q, Qz = tb.N[2] * tb.q;
+  const size_t Q3 = size_t(Qx) * Qy * Qz;
   for (size_t idx = size_t(blockIdx.x) * blockDim.x + threadIdx.x; idx < Q3;
        idx += size_t(gridDim.x) * blockDim.x) {
-    const int a = int(idx % Q), b = int((idx / Q) % Q), c = int(idx / (size_t(Q) * Q));
+    const int a = int(idx % Qx), b = int((idx / Qx) % Qy), c = int(idx / (size_t(Qx) * Qy));
     double e[3], h[3];
-    exact(tb.x[a], tb.x[b], tb.x[c], t, e, h, nullptr, nullptr);
+    exact(tb.x[0][a], tb.x[1][b], tb.x[2][c], t, e, h, nullptr, nullptr);
     for (int k = 0; k < 3; ++k) {
       vals[k * Q3 + idx] = e[k];
       vals[(3 + k) * Q3 + idx] = h[k];
@@ -55,32 +55,34 @@ __global__ void exact_kernel(Tables tb, double t, double* vals) {
 // of its support and their Gauss points.
 template <typename T>
 __global__ void project_rhs_kernel(Tables tb, const double* __restrict__ vals, T* __restrict__ st) {
-  const int N = tb.N, p = tb.p, q = tb.q, n = N + p, Q = N * q;
-  const size_t Q3 = size_t(Q) * Q * Q, D = size_t(n) * n * n;
+  const int p = tb.p, q = tb.q;
+  const int nx = tb.N[0] + p, ny = tb.N[1] + p, nz = tb.N[2] + p;
+  const int Qx = tb.N[0] * q, Qy = tb.N[1] * q;
+  const size_t Q3 = size_t(Qx) * Qy * (tb.N[2] * q), D = size_t(nx) * ny * nz;
   for (size_t idx = size_t(blockIdx.x) * blockDim.x + threadIdx.x; idx < 6 * D;
        idx += size_t(gridDim.x) * blockDim.x) {
     const int comp = int(idx / D);
     const size_t o = idx % D;
-    const int i = int(o % n), j = int((o / n) % n), k = int(o / (size_t(n) * n));
-    const bool bi = i == 0 || i == n - 1, bj = j == 0 || j == n - 1, bk = k == 0 || k == n - 1;
+    const int i = int(o % nx), j = int((o / nx) % ny), k = int(o / (size_t(nx) * ny));
+    const bool bi = i == 0 || i == nx - 1, bj = j == 0 || j == ny - 1, bk = k == 0 || k == nz - 1;
     const int cc = comp % 3;
     const bool bnd = comp < 3 ? ((cc != 0 && bi) || (cc != 1 && bj) || (cc != 2 && bk))
                               : ((cc == 0 && bi) || (cc == 1 && bj) || (cc == 2 && bk));
     double s = 0.0;
     if (!bnd) {
-      for (int ez = max(k - p, 0); ez <= min(k, N - 1); ++ez)
-        for (int ey = max(j - p, 0); ey <= min(j, N - 1); ++ey)
-          for (int ex = max(i - p, 0); ex <= min(i, N - 1); ++ex)
+      for (int ez = max(k - p, 0); ez <= min(k, tb.N[2] - 1); ++ez)
+        for (int ey = max(j - p, 0); ey <= min(j, tb.N[1] - 1); ++ey)
+          for (int ex = max(i - p, 0); ex <= min(i, tb.N[0] - 1); ++ex)
             for (int gz = 0; gz < q; ++gz) {
               const int c = ez * q + gz;
-              const double wz = tb.w[c] * tb.bv[c * (p + 1) + (k - ez)];
+              const double wz = tb.w[2][c] * tb.bv[2][c * (p + 1) + (k - ez)];
               for (int gy = 0; gy < q; ++gy) {
                 const int b = ey * q + gy;
-                const double wy = wz * tb.w[b] * tb.bv[b * (p + 1) + (j - ey)];
+                const double wy = wz * tb.w[1][b] * tb.bv[1][b * (p + 1) + (j - ey)];
                 for (int gx = 0; gx < q; ++gx) {
                   const int a = ex * q + gx;
-                  s += wy * tb.w[a] * tb.bv[a * (p + 1) + (i - ex)] *
-                       vals[comp * Q3 + (size_t(c) * Q + b) * Q + a];
+                  s += wy * tb.w[0][a] * tb.bv[0][a * (p + 1) + (i - ex)] *
+                       vals[comp * Q3 + (size_t(c) * Qy + b) * Qx + a];
                 }
               }
             }
@@ -95,19 +97,21 @@ __global__ void project_rhs_kernel(Tables tb, const double* __restrict__ vals, T
 template <typename T>
 __global__ __launch_bounds__(256) void errors_kernel(Tables tb, const T* __restrict__ st, double t,
                                                      double* __restrict__ partial) {
-  const int N = tb.N, p = tb.p, q = tb.q, n = N + p, Q = N * q;
-  const size_t Q3 = size_t(Q) * Q * Q, D = size_t(n) * n * n;
+  const int p = tb.p, q = tb.q;
+  const int nx = tb.N[0] + p, ny = tb.N[1] + p, nz = tb.N[2] + p;
+  const int Qx = tb.N[0] * q, Qy = tb.N[1] * q;
+  const size_t Q3 = size_t(Qx) * Qy * (tb.N[2] * q), D = size_t(nx) * ny * nz;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   for (size_t idx = size_t(blockIdx.x) * blockDim.x + threadIdx.x; idx < Q3;
        idx += size_t(gridDim.x) * blockDim.x) {
-    const int a = int(idx % Q), b = int((idx / Q) % Q), c = int(idx / (size_t(Q) * Q));
+    const int a = int(idx % Qx), b = int((idx / Qx) % Qy), c = int(idx / (size_t(Qx) * Qy));
     const int fx = a / q, fy = b / q, fz = c / q;
-    const double* vx = tb.bv + a * (p + 1);
-    const double* vy = tb.bv + b * (p + 1);
-    const double* vz = tb.bv + c * (p + 1);
-    const double* dx = tb.bd + a * (p + 1);
-    const double* dy = tb.bd + b * (p + 1);
-    const double* dz = tb.bd + c * (p + 1);
+    const double* vx = tb.bv[0] + a * (p + 1);
+    const double* vy = tb.bv[1] + b * (p + 1);
+    const double* vz = tb.bv[2] + c * (p + 1);
+    const double* dx = tb.bd[0] + a * (p + 1);
+    const double* dy = tb.bd[1] + b * (p + 1);
+    const double* dz = tb.bd[2] + c * (p + 1);
     // f[comp][0] value, [1] d/dx, [2] d/dy, [3] d/dz
     double f[6][4];
     for (int comp = 0; comp < 6; ++comp) {
@@ -115,7 +119,7 @@ __global__ __launch_bounds__(256) void errors_kernel(Tables tb, const T* __restr
       double v0 = 0, v1 = 0, v2 = 0, v3 = 0;
       for (int r = 0; r <= p; ++r)
         for (int sidx = 0; sidx <= p; ++sidx) {
-          const T* row = cf + (size_t(fz + r) * n + (fy + sidx)) * n + fx;
+          const T* row = cf + (size_t(fz + r) * ny + (fy + sidx)) * nx + fx;
           double rv = 0.0, rd = 0.0;
           for (int u = 0; u <= p; ++u) {
             const double cval = double(row[u]);
@@ -130,8 +134,8 @@ __global__ __launch_bounds__(256) void errors_kernel(Tables tb, const T* __restr
       f[comp][0] = v0; f[comp][1] = v1; f[comp][2] = v2; f[comp][3] = v3;
     }
     double e[3], h[3], ce[3], ch[3];
-    exact(tb.x[a], tb.x[b], tb.x[c], t, e, h, ce, ch);
-    const double wq = tb.w[a] * tb.w[b] * tb.w[c];
+    exact(tb.x[0][a], tb.x[1][b], tb.x[2][c], t, e, h, ce, ch);
+    const double wq = tb.w[0][a] * tb.w[1][b] * tb.w[2][c];
     for (int fld = 0; fld < 2; ++fld) {
       const double (*F)[4] = f + 3 * fld;
       const double* ex = fld ? h : e;
@@ -191,24 +195,24 @@ hipError_t noalloc_scratch(double** out) {
 }
 
 hipError_t launch_exact(const Tables& tb, double t, double* vals, hipStream_t s) {
-  const size_t Q = size_t(tb.N) * tb.q;
-  hipLaunchKernelGGL(exact_kernel, dim3(grid_for(Q * Q * Q)), dim3(256), 0, s, tb, t, vals);
+  const size_t Q3 = size_t(tb.N[0]) * tb.q * size_t(tb.N[1]) * tb.q * size_t(tb.N[2]) * tb.q;
+  hipLaunchKernelGGL(exact_kernel, dim3(grid_for(Q3)), dim3(256), 0, s, tb, t, vals);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_project_rhs(const Tables& tb, const double* vals, T* state, hipStream_t s) {
-  const size_t n = size_t(tb.N) + tb.p;
-  hipLaunchKernelGGL(project_rhs_kernel<T>, dim3(grid_for(6 * n * n * n)), dim3(256), 0, s, tb,
-                     vals, state);
+  const size_t D = (size_t(tb.N[0]) + tb.p) * (size_t(tb.N[1]) + tb.p) * (size_t(tb.N[2]) + tb.p);
+  hipLaunchKernelGGL(project_rhs_kernel<T>, dim3(grid_for(6 * D)), dim3(256), 0, s, tb, vals,
+                     state);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_errors(const Tables& tb, const T* state, double t, double* partial, int* nblk,
                          hipStream_t s) {
-  const size_t Q = size_t(tb.N) * tb.q;
-  const int g = grid_for(Q * Q * Q);
+  const size_t Q3 = size_t(tb.N[0]) * tb.q * size_t(tb.N[1]) * tb.q * size_t(tb.N[2]) * tb.q;
+  const int g = grid_for(Q3);
   *nblk = g;
   hipLaunchKernelGGL(errors_kernel<T>, dim3(g), dim3(256), 0, s, tb, state, t, partial);
   return hipGetLastError();

@@ -6,9 +6,6 @@
 namespace adimx {
 namespace mms {
 
-// Quadrature tables of one axis: Q = N q Gauss points, for point a the
-// basis functions a/q .. a/q + p (element a/q) with values bv[a*(p+1) + r]
-// and derivatives bd[a*(p+1) + r]; coordinates x[a] and weights w[a].
 constexpr int kMaxErrorBlocks = 2048;
 
 // Size of the fixed device array behind adi_mms_errors_noalloc (one copy per
@@ -19,19 +16,24 @@ constexpr size_t kNoAllocScratchBytes = size_t(1) << 20;
 // hipGetSymbolAddress once per device, then cached).
 hipError_t noalloc_scratch(double** out);
 
+// Quadrature tables per axis a (x, y, z): Q_a = N_a q Gauss points, for
+// point g the basis functions g/q .. g/q + p (element g/q) with values
+// bv[a][g*(p+1) + r] and derivatives bd[a][g*(p+1) + r]; coordinates x[a][g]
+// and weights w[a][g].
 struct Tables {
-  const double* x;
-  const double* w;
-  const double* bv;
-  const double* bd;
-  int N, p, q;
+  const double* x[3];
+  const double* w[3];
+  const double* bv[3];
+  const double* bd[3];
+  int N[3], p, q;
 };
 
-// vals[c * Q^3 + point] = component c (E1..E3, H1..H3) of the manufactured
-// solution at time t on the tensor grid of quadrature points (x fastest).
+// vals[c * Qx Qy Qz + point] = component c (E1..E3, H1..H3) of the
+// manufactured solution at time t on the tensor grid of quadrature points
+// (x fastest).
 hipError_t launch_exact(const Tables& tb, double t, double* vals, hipStream_t s);
 // L2 projection right-hand sides (f_c, B_i B_j B_k) into the six state
-// components (type T, n^3 each), constrained coefficients set to zero.
+// components (type T, nx ny nz each), constrained coefficients set to zero.
 template <typename T>
 hipError_t launch_project_rhs(const Tables& tb, const double* vals, T* state, hipStream_t s);
 // Per-block partial sums of the squared errors of the state against the

@@ -15,11 +15,12 @@ PRECISIONS = {"fp64": _lib.ADI_FP64, "fp32_refine": _lib.ADI_FP32_REFINE}
 
 
 class Solver:
-    """ADI time stepper for an N^3-element patch of degree-p B-splines.
+    """ADI time stepper for a patch of degree-p B-splines.
 
     Parameters
     ----------
-    N, p : elements per axis and B-spline degree (1 <= p <= 4).
+    N : elements per axis (an int for a cube, or (Nx, Ny, Nz)).
+    p : B-spline degree (1 <= p <= 4).
     precision : "fp64" or "fp32_refine".
     device : torch device string; its current stream is used.
     """
@@ -31,13 +32,18 @@ class Solver:
         self.lib = _lib.load()
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible: the ADI step runs only in the HIP library")
-        self.N, self.p = int(N), int(p)
-        self.n = self.N + self.p
+        self.p = int(p)
+        self.Ns = tuple(int(v) for v in np.broadcast_to(np.asarray(N), (3,)))
+        self.dims = tuple(v + self.p for v in self.Ns)          # (nx, ny, nz)
+        self.shape = (self.dims[2], self.dims[1], self.dims[0])  # arrays: [z][y][x]
+        self.D = int(np.prod(self.dims))
+        if len(set(self.Ns)) == 1:  # a cube: one element count for every axis
+            self.N, self.n = self.Ns[0], self.dims[0]
         self.precision = precision
         self.device = torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         h = ctypes.c_void_p()
-        st = self.lib.adi_create(ctypes.byref(h), self.N, self.N, self.N, self.p,
+        st = self.lib.adi_create(ctypes.byref(h), *self.Ns, self.p,
                                  PRECISIONS[precision], ctypes.c_void_p(self.stream.cuda_stream))
         if st != 0:
             raise _lib.AdiError(st, "adi_create")
@@ -83,8 +89,8 @@ class Solver:
                                               Vx, Vy, Vz, self.MAPS[mapping]))
 
     def set_material_dof(self, eps, mu, sigma_nd):
-        D = self.n ** 3
-        e, m, s = (self._arr(np.broadcast_to(np.asarray(v, float), (self.n,) * 3), D)
+        D = self.D
+        e, m, s = (self._arr(np.broadcast_to(np.asarray(v, float), self.shape), D)
                    for v in (eps, mu, sigma_nd))
         self._check(self.lib.adi_set_material_dof(self.h, _lib.dptr(e), _lib.dptr(m), _lib.dptr(s)))
 
@@ -98,7 +104,7 @@ class Solver:
         if tau is None:
             self._check(self.lib.adi_set_local_dt(self.h, None))
             return
-        a = self._arr(np.broadcast_to(np.asarray(tau, float), (self.n,) * 3), self.n ** 3)
+        a = self._arr(np.broadcast_to(np.asarray(tau, float), self.shape), self.D)
         self._check(self.lib.adi_set_local_dt(self.h, _lib.dptr(a)))
 
     def factor(self, dt: float):
@@ -106,11 +112,11 @@ class Solver:
 
     # -- state ---------------------------------------------------------------
     def set_fields(self, EH, t: float = 0.0):
-        a = self._arr(EH, 6 * self.n ** 3)
+        a = self._arr(EH, 6 * self.D)
         self._check(self.lib.adi_set_fields(self.h, _lib.dptr(a), float(t)))
 
     def get_fields(self):
-        out = np.empty((6, self.n, self.n, self.n))
+        out = np.empty((6,) + self.shape)
         t = ctypes.c_double()
         self._check(self.lib.adi_get_fields(self.h, _lib.dptr(out), ctypes.byref(t)))
         return out, t.value
@@ -151,16 +157,16 @@ class Solver:
     # -- single stages (testing) ---------------------------------------------
     def rhs(self, stage: int, sub: int, fields, t: float = 0.0):
         nf = 6 if stage == 0 else 9
-        a = self._arr(fields, nf * self.n ** 3)
-        out = np.empty((3, self.n, self.n, self.n))
+        a = self._arr(fields, nf * self.D)
+        out = np.empty((3,) + self.shape)
         self._check(self.lib.adi_rhs(self.h, int(stage), int(sub), _lib.dptr(a), float(t),
                                      _lib.dptr(out)))
         return out
 
     def solve(self, stage: int, sub: int, rhs):
-        a = self._arr(rhs, 3 * self.n ** 3).copy()
+        a = self._arr(rhs, 3 * self.D).copy()
         self._check(self.lib.adi_solve(self.h, int(stage), int(sub), _lib.dptr(a)))
-        return a.reshape(3, self.n, self.n, self.n)
+        return a.reshape((3,) + self.shape)
 
     # -- learned closure (solver side) ----------------------------------------
     def copy_state_from(self, other: "Solver"):
@@ -201,9 +207,8 @@ class Solver:
 
     def project(self, vals_qp, q: int, t: float = 0.0):
         """State = L2 projection of six component fields given at the Gauss
-        points (array (6, N q, N q, N q), x fastest), time t."""
-        Q = self.N * int(q)
-        a = self._arr(vals_qp, 6 * Q ** 3)
+        points (array (6, Nz q, Ny q, Nx q), x fastest), time t."""
+        a = self._arr(vals_qp, 6 * int(np.prod([Na * int(q) for Na in self.Ns])))
         self._check(self.lib.adi_project(self.h, _lib.dptr(a), int(q), float(t)))
 
     def mms_errors_noalloc(self, q: int = 0) -> dict:

@@ -53,7 +53,16 @@ def test_host_validation_errors(lib):
     assert lib.adi_create(ctypes.byref(h), 0, 0, 0, 2, 0, None) == _lib.ADI_EINVAL
     assert lib.adi_create(ctypes.byref(h), 4, 4, 4, 0, 0, None) == _lib.ADI_EINVAL
     assert lib.adi_create(ctypes.byref(h), 4, 4, 4, 5, 0, None) == _lib.ADI_EINVAL
-    assert lib.adi_create(ctypes.byref(h), 4, 5, 4, 2, 0, None) == _lib.ADI_EINVAL
+    assert lib.adi_create(ctypes.byref(h), 4, 0, 4, 2, 0, None) == _lib.ADI_EINVAL
+    # (nx+p)(ny+p)(nz+p) coefficients per component must stay below 2^31
+    assert lib.adi_create(ctypes.byref(h), 1290, 1290, 1290, 1, 0, None) == _lib.ADI_EINVAL
+    # element counts may differ per axis
+    assert lib.adi_create(ctypes.byref(h), 4, 5, 6, 2, 0, None) == _lib.ADI_OK
+    dims = (ctypes.c_int * 3)()
+    assert lib.adi_dims(h, dims) == _lib.ADI_OK and list(dims) == [6, 7, 8]
+    assert lib.adi_ncoef(h) == 6
+    assert lib.adi_workspace_bytes(h) > 6 * 6 * 7 * 8 * 8
+    lib.adi_destroy(h)
     assert lib.adi_create(ctypes.byref(h), 4, 4, 4, 2, 7, None) == _lib.ADI_EINVAL
     st, h = _ctx(lib)
     assert st == _lib.ADI_OK

@@ -196,6 +196,26 @@ def test_cyclic_equivariance_constant_material():
         np.testing.assert_allclose(b, a, atol=1e-12)
 
 
+def test_cyclic_equivariance_non_cubic_patch():
+    """On a patch of Nx x Ny x Nz elements the relabelling x -> y -> z -> x
+    turns it into a patch of Nz x Nx x Ny elements: stepping and rotating
+    commute with varying material too (each axis keeps its own 1D matrices;
+    a mix-up of two axes' matrices breaks this)."""
+    Ns, p = (2, 3, 4), 2
+    shape = (Ns[2] + p, Ns[1] + p, Ns[0] + p)
+    rng = np.random.default_rng(12)
+    eps, mu, sig = rng.uniform(1, 20, shape), rng.uniform(0.5, 2, shape), rng.uniform(0, 5, shape)
+    prob = maxwell.Problem(Ns, p, eps, mu, sig, 0.07)
+    rot = maxwell.Problem((Ns[2], Ns[0], Ns[1]), p, _rot(eps), _rot(mu), _rot(sig), 0.07)
+    F = rng.standard_normal((6,) + shape)
+    E, H = prob.constrain(list(F[:3]), list(F[3:]))
+    rotE = lambda E: [_rot(E[2]), _rot(E[0]), _rot(E[1])]
+    E1, H1, _ = prob.step(E, H, 0.0)
+    E2, H2, _ = rot.step(rotE(E), rotE(H), 0.0)
+    for a, b in zip(rotE(E1) + rotE(H1), E2 + H2):
+        np.testing.assert_allclose(b, a, atol=1e-12 * np.abs(a).max())
+
+
 def _step_matrix(prob):
     """Dense matrix of one step on the constrained state space (J = 0)."""
     n = prob.n

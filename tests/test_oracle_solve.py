@@ -56,28 +56,31 @@ def test_constant_sweeps_equal_dense_kronecker_solve(N, p):
     np.testing.assert_allclose(u, ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
 
 
+@pytest.mark.parametrize("Ns", [(3, 3, 3), (2, 3, 4)])
 @pytest.mark.parametrize("c,sub", [(0, 1), (1, 1), (2, 1), (0, 2), (1, 2), (2, 2)])
-def test_modified_solve_equals_dense_row_scaled_kronecker(c, sub):
+def test_modified_solve_equals_dense_row_scaled_kronecker(c, sub, Ns):
     """Varying material: the E_c solve equals the dense solve of the row-scaled
     global system of eq. dupa1ab, M..(M + diag(alpha) S)..M restricted to the
-    constrained space (reading R6: the modified axis is solved first)."""
-    N, p = 3, 2
-    M, S, _, _ = gram.gram_matrices(N, p)
-    n = N + p
+    constrained space (reading R6: the modified axis is solved first); also on
+    a patch with a different element count per axis, each axis with its own
+    1D matrices."""
+    p = 2
+    G1 = [gram.gram_matrices(Na, p) for Na in Ns]
+    shape = (Ns[2] + p, Ns[1] + p, Ns[0] + p)
     rng = np.random.default_rng(2 + c)
-    eps = rng.uniform(1.0, 50.0, (n, n, n))
-    prob = maxwell.Problem(N, p, eps, 1.0, 0.0, 0.2)
+    eps = rng.uniform(1.0, 50.0, shape)
+    prob = maxwell.Problem(Ns, p, eps, 1.0, 0.0, 0.2)
     alpha = prob.coef["alpha"]
     mod = maxwell.MOD_AXIS[sub][c]
-    rhs = maxwell.zero_boundary(rng.standard_normal((n, n, n)), maxwell.dirichlet_axes("E", c))
+    rhs = maxwell.zero_boundary(rng.standard_normal(shape), maxwell.dirichlet_axes("E", c))
     u = prob.solve3(rhs, "E", c, mod)
-    mats = [M, M, M]
+    mats = [G1[a][0] for a in range(3)]
     plain = kron3(*mats)
-    mats[mod] = S
+    mats[mod] = G1[mod][1]
     stiff = kron3(*mats)
     G = plain + alpha.ravel()[:, None] * stiff
-    free = _free_mask(n, "E")[c * n ** 3:(c + 1) * n ** 3]
-    ref = np.zeros(n ** 3)
+    free = _free_mask(shape, "E")[c]
+    ref = np.zeros(rhs.size)
     ref[free] = np.linalg.solve(G[np.ix_(free, free)], rhs.ravel()[free])
     np.testing.assert_allclose(u.ravel(), ref, rtol=1e-11, atol=1e-12 * np.abs(ref).max())
 
@@ -85,47 +88,52 @@ def test_modified_solve_equals_dense_row_scaled_kronecker(c, sub):
 # ---------------------------------------------------------------------------
 # Dense assembly of discrete1-discrete4 straight from the block-matrix list.
 
-def _blocks(M, S, A, B):
-    k = kron3
-    Z = np.zeros_like(k(M, M, M))
-    MMM = k(M, M, M)
+def _blocks(G1):
+    """Block matrices from the 1D matrices of each axis, G1[a] = (M, S, A, B);
+    "XYZ" is X of the x axis (x) Y of the y axis (x) Z of the z axis."""
+    idx = {"M": 0, "S": 1, "A": 2, "B": 3}
+    k = lambda ops: kron3(*(G1[a][idx[o]] for a, o in enumerate(ops)))
+    MMM = k("MMM")
+    Z = np.zeros_like(MMM)
     blk = lambda rows: np.block(rows)
     return dict(
         M=blk([[MMM, Z, Z], [Z, MMM, Z], [Z, Z, MMM]]),
-        K1=blk([[k(M, S, M), Z, Z], [Z, k(M, M, S), Z], [Z, Z, k(S, M, M)]]),
-        K2=blk([[k(M, M, S), Z, Z], [Z, k(S, M, M), Z], [Z, Z, k(M, S, M)]]),
-        R1=blk([[Z, k(A, B, M), Z], [Z, Z, k(M, A, B)], [k(B, M, A), Z, Z]]),
-        R2=blk([[Z, Z, k(A, M, B)], [k(B, A, M), Z, Z], [Z, k(M, B, A), Z]]),
-        C1=blk([[Z, Z, k(M, A, M)], [k(M, M, A), Z, Z], [Z, k(A, M, M), Z]]),
+        K1=blk([[k("MSM"), Z, Z], [Z, k("MMS"), Z], [Z, Z, k("SMM")]]),
+        K2=blk([[k("MMS"), Z, Z], [Z, k("SMM"), Z], [Z, Z, k("MSM")]]),
+        R1=blk([[Z, k("ABM"), Z], [Z, Z, k("MAB")], [k("BMA"), Z, Z]]),
+        R2=blk([[Z, Z, k("AMB")], [k("BAM"), Z, Z], [Z, k("MBA"), Z]]),
+        C1=blk([[Z, Z, k("MAM")], [k("MMA"), Z, Z], [Z, k("AMM"), Z]]),
         # block (3,1) fixed to M (x) A (x) M (reading R1)
-        C2=blk([[Z, k(M, M, A), Z], [Z, Z, k(A, M, M)], [k(M, A, M), Z, Z]]),
+        C2=blk([[Z, k("MMA"), Z], [Z, Z, k("AMM")], [k("MAM"), Z, Z]]),
     )
 
 
-def _free_mask(n, kind):
-    """Boolean mask over the 3 n^3 unknowns of E or H that are not constrained."""
+def _free_mask(shape, kind):
+    """Per component: boolean mask over the unknowns of E_c or H_c (array
+    shape (nz, ny, nx)) that are not constrained."""
     masks = []
     for c in range(3):
-        m = np.ones((n, n, n), bool)
+        m = np.ones(shape, bool)
         for a in maxwell.dirichlet_axes(kind, c):
             ax = maxwell._NP_AXIS[a]
             idx = [slice(None)] * 3
-            for b in (0, n - 1):
+            for b in (0, shape[ax] - 1):
                 idx[ax] = b
                 m[tuple(idx)] = False
         masks.append(m.ravel())
-    return np.concatenate(masks)
+    return masks
 
 
 def _dense_step(N, p, eps, mu, sig, dt, src, E, H, t, tau=None):
     """One step from the dense block systems; eps, mu, sig scalars or per-DOF
     arrays (material attached to test functions = rows, reading R4/R5); tau
     a per-row time step in the row coefficients (default dt)."""
-    M, S, A, B = gram.gram_matrices(N, p)
-    n = N + p
-    K = _blocks(M, S, A, B)
+    Ns = maxwell.axis_counts(N)
+    shape = (Ns[2] + p, Ns[1] + p, Ns[0] + p)
+    D = int(np.prod(shape))
+    K = _blocks([gram.gram_matrices(Na, p) for Na in Ns])
     C = K["C1"] - K["C2"]
-    full = lambda v: np.tile(np.broadcast_to(np.asarray(v, float), (n, n, n)).ravel(), 3)
+    full = lambda v: np.tile(np.broadcast_to(np.asarray(v, float), shape).ravel(), 3)
     eps, mu, sig = full(eps), full(mu), full(sig)
     tr = full(dt if tau is None else tau)
     c = sig * tr / (4 * eps)
@@ -133,15 +141,15 @@ def _dense_step(N, p, eps, mu, sig, dt, src, E, H, t, tau=None):
     b = tr / (2 * eps * (1 + c))
     g = (1 - c) / (1 + c)
     d = tr / (2 * mu)
-    fe, fh = _free_mask(n, "E"), _free_mask(n, "H")
-    knots = bspline.open_uniform_knots(N, p)
+    fe, fh = np.concatenate(_free_mask(shape, "E")), np.concatenate(_free_mask(shape, "H"))
 
     def J(tt):
-        v = np.zeros(3 * n ** 3)
+        v = np.zeros(3 * D)
         if src is not None:
-            bx, by, bz = (bspline.basis(knots, p, [s])[0] for s in src.xs)
+            bx, by, bz = (bspline.basis(bspline.open_uniform_knots(Ns[a], p), p, [src.xs[a]])[0]
+                          for a in range(3))
             g_t = np.sin(2 * np.pi * src.f0 * (tt - src.t0)) * np.exp(-((tt - src.t0) / src.width) ** 2)
-            v[src.comp * n ** 3:(src.comp + 1) * n ** 3] = src.amp * g_t * np.einsum(
+            v[src.comp * D:(src.comp + 1) * D] = src.amp * g_t * np.einsum(
                 "k,j,i->kji", bz, by, bx).ravel()
         return v
 
@@ -161,8 +169,7 @@ def _dense_step(N, p, eps, mu, sig, dt, src, E, H, t, tau=None):
                + a * (K["R2"] @ e1) - b * J(t + 3 * dt / 4), fe)
     # discrete4 with the sign of scheme1d (reading R2)
     h2 = solve(K["M"], K["M"] @ h1 + d * (K["C2"] @ e1) - d * (K["C1"] @ e2), fh)
-    sh = (n, n, n)
-    return ([x.reshape(sh) for x in np.split(e2, 3)], [x.reshape(sh) for x in np.split(h2, 3)])
+    return ([x.reshape(shape) for x in np.split(e2, 3)], [x.reshape(shape) for x in np.split(h2, 3)])
 
 
 @pytest.mark.parametrize("N,p,eps,mu,sig,dt,with_src", [
@@ -172,16 +179,23 @@ def _dense_step(N, p, eps, mu, sig, dt, src, E, H, t, tau=None):
     (3, 1, 1.0, 2.0, 10.0, 0.05, False),
     (3, 2, "rand", "rand", "rand", 0.1, True),
     (2, 3, "rand", 1.0, "rand", 0.3, True),
+    ((1, 2, 3), 2, "rand", "rand", "rand", 0.1, True),
+    ((3, 1, 2), 3, "rand", 1.0, "rand", 0.2, True),
+    ((2, 4, 1), 1, 1.5, 0.8, 2.0, 0.07, True),
 ])
 def test_full_step_equals_dense_block_solve(N, p, eps, mu, sig, dt, with_src):
-    n = N + p
+    """One oracle step against the dense block systems, also on patches with
+    a different element count per axis (the paper reorders each right-hand
+    side into N_x rows of N_y N_z columns, which allows N_x != N_y != N_z)."""
+    Ns = maxwell.axis_counts(N)
+    shape = (Ns[2] + p, Ns[1] + p, Ns[0] + p)
     rng = np.random.default_rng(17)
-    rnd = lambda v, lo, hi: rng.uniform(lo, hi, (n, n, n)) if v == "rand" else v
+    rnd = lambda v, lo, hi: rng.uniform(lo, hi, shape) if v == "rand" else v
     eps, mu, sig = rnd(eps, 1.0, 50.0), rnd(mu, 0.5, 2.0), rnd(sig, 0.0, 20.0)
     src = DipoleSource(xs=(0.41, 0.55, 0.37), comp=1, amp=0.8, f0=1.5, t0=0.1, width=0.3) \
         if with_src else None
     prob = maxwell.Problem(N, p, eps, mu, sig, dt, src)
-    F = random_fields(n, seed=5)
+    F = np.random.default_rng(5).standard_normal((6,) + shape)
     E, H = prob.constrain(list(F[:3]), list(F[3:]))
     t = 0.03
     E1, H1, t1 = prob.step(E, H, t)
@@ -201,8 +215,7 @@ def test_rhs_rows_with_varying_material_equal_dense_row_scaling():
     sig = rng.uniform(0, 20, (n, n, n))
     dt = 0.05
     prob = maxwell.Problem(N, p, eps, mu, sig, dt)
-    M, S, A, B = gram.gram_matrices(N, p)
-    K = _blocks(M, S, A, B)
+    K = _blocks([gram.gram_matrices(N, p)] * 3)
     F = random_fields(n, seed=8)
     E, H = prob.constrain(list(F[:3]), list(F[3:]))
     e, h = np.concatenate([x.ravel() for x in E]), np.concatenate([x.ravel() for x in H])
@@ -210,7 +223,7 @@ def test_rhs_rows_with_varying_material_equal_dense_row_scaling():
     rep = lambda v: np.tile(v.ravel(), 3)
     dense = rep(co["gamma"]) * (K["M"] @ e) + rep(co["beta"]) * ((K["C1"] - K["C2"]) @ h) \
         + rep(co["alpha"]) * (K["R1"] @ e)
-    fe = _free_mask(n, "E")
+    fe = np.concatenate(_free_mask((n, n, n), "E"))
     dense[~fe] = 0.0
     fields = {"E1": E[0], "E2": E[1], "E3": E[2], "H1": H[0], "H2": H[1], "H3": H[2]}
     mine = np.concatenate([prob.rhs_E(1, fields, c, 0.0).ravel() for c in range(3)])
