@@ -82,7 +82,8 @@ int adi_dims(const adi_ctx* ctx, int* n_out);
 
 /*
  * Bytes of device memory the context needs once factored (fields, scratch,
- * coefficients, per-line factors).  A caller that wants to own the memory
+ * coefficients, per-line factors; the data of the time step of section
+ * "Alternating directions splitting for Maxwell equations").  A caller that wants to own the memory
  * (e.g. a PyTorch tensor) allocates this many bytes, 256-byte aligned, and
  * binds it before adi_factor.  Returns 0 for an invalid handle.
  */
@@ -104,18 +105,36 @@ int adi_bind_workspace(adi_ctx* ctx, void* dev_ptr, size_t bytes);
 int adi_set_material(adi_ctx* ctx, const double* eps_r, const double* mu_r,
                      const double* sigma_nd, int vx, int vy, int vz, int map_mode);
 
-/* Material given directly per degree of freedom (three D arrays, x fastest). */
+/* Material given directly per degree of freedom (three D arrays, x fastest):
+ * the per-test-function eps, mu of section "Incorporating non-regular
+ * material data" (eq. dupa1abcdefg), and sigma_nd.  Copied; EINVAL as above. */
 int adi_set_material_dof(adi_ctx* ctx, const double* eps, const double* mu, const double* sigma_nd);
 
 /*
- * Build the 1D Gram matrices M, S, A, B (float64, exact Gauss quadrature),
- * the per-row coefficients for time step dt (alpha, beta, gamma, delta) and
- * the pivot-free banded LU factors, in float64: shared factors of the
- * unmodified 1D matrices and per-line factors of the material-modified
- * ones.  ESINGULAR if a pivot is below 1e-14 times its diagonal entry.
- * ESTATE if no material was set.
+ * Build, for time step dt >= 0, the 1D Gram matrices M, S, A, B of every
+ * axis (float64, exact Gauss quadrature; the matrix list after eqs.
+ * discrete1-discrete4 in section "Variational formulation"), the per-row
+ * coefficients alpha, beta, gamma, delta of discrete1-discrete4 (with the
+ * conductivity terms), and the pivot-free banded LU factors of the 1D
+ * systems of section "Incorporating non-regular material data" (the three
+ * systems after eq. dupa1abcdefg), in float64: shared factors of the
+ * unmodified 1D mass matrices and per-line factors of the material-modified
+ * ones.  Captures the time step as a HIP graph.  ESINGULAR if a pivot's
+ * magnitude falls to or below the pivot floor (adi_set_pivot_floor, default
+ * 1e-14) times its diagonal entry; ESTATE if no material was set; EINVAL for
+ * a dt that is negative or not finite.  Allocates the workspace on first use
+ * unless one was bound.
  */
 int adi_factor(adi_ctx* ctx, double dt);
+
+/*
+ * Smallest accepted ratio |U_rr| / |A_rr| of a pivot to its diagonal entry
+ * in adi_factor's pivot-free LU (the paper does not say how the banded
+ * systems are factorised; without pivoting, this check guards the
+ * factorisation).  floor must be finite and >= 0; default 1e-14.  Takes
+ * effect at the next adi_factor.
+ */
+int adi_set_pivot_floor(adi_ctx* ctx, double floor);
 
 /*
  * Point dipole source J = amp g(t) e_comp delta(x - xs) with
@@ -127,7 +146,11 @@ int adi_factor(adi_ctx* ctx, double dt);
 int adi_set_source(adi_ctx* ctx, const double xs[3], int comp, double amp, double f0,
                    double t0, double width);
 
-/* Upload a state (6 D float64, layout above) and set the time t. */
+/* Upload a state (6 D float64, layout above: E^n and H^n of the scheme of
+ * section "Alternating directions splitting for Maxwell equations", with the
+ * PEC-constrained coefficients expected to be zero) and set the time t.
+ * Copied; waits for the context's stream; ENONFINITE for a value that is not
+ * finite. */
 int adi_set_fields(adi_ctx* ctx, const double* EH, double t);
 
 /*
@@ -142,12 +165,16 @@ int adi_set_fields(adi_ctx* ctx, const double* EH, double t);
 int adi_set_local_dt(adi_ctx* ctx, const double* tau);
 
 /*
- * Enqueue nsteps full time steps on the context's stream and return without
- * waiting.  Each step is one replay of a captured HIP graph.
+ * Enqueue nsteps full time steps n -> n+1 (both substeps of eqs.
+ * scheme1a-scheme1d, discretised as discrete1-discrete4) on the context's
+ * stream and return without waiting.  Each step is one replay of a captured
+ * HIP graph.  ESTATE before a successful adi_factor; EINVAL for nsteps < 0.
  */
 int adi_step(adi_ctx* ctx, int nsteps);
 
-/* Wait for the stream, then copy the state to EH_out (float64) and t to *t_out. */
+/* Wait for the stream, then copy the state E^n, H^n (6 D float64, layout
+ * above; the float32 mode's state converted) to EH_out and the time to
+ * *t_out (may be NULL).  ESTATE before any state exists. */
 int adi_get_fields(adi_ctx* ctx, double* EH_out, double* t_out);
 
 /*
@@ -157,7 +184,7 @@ int adi_get_fields(adi_ctx* ctx, double* EH_out, double* t_out);
  */
 int adi_fields_device(adi_ctx* ctx, void** dev, int* dtype);
 
-/* Wait for all work enqueued by the context. */
+/* Wait for all work enqueued by the context (its stream). */
 int adi_sync(adi_ctx* ctx);
 
 /*
@@ -178,7 +205,10 @@ int adi_profile_run(adi_ctx* ctx, int nsteps);
 int adi_profile_read(adi_ctx* ctx, int cap, int* nout, int* kind, int* ndesc, int* nmod,
                      int* nacc, float* ms);
 
+/* Message of the context's last error ("invalid handle" for NULL). */
 const char* adi_last_error(const adi_ctx* ctx);
+/* Wait for the context's stream and free everything the library allocated
+ * for it (a bound workspace stays the caller's). */
 void adi_destroy(adi_ctx* ctx);
 
 /*

@@ -33,6 +33,7 @@ SIGNATURES = {
     "adi_set_material": (_I, [_P, _D, _D, _D, _I, _I, _I, _I]),
     "adi_set_material_dof": (_I, [_P, _D, _D, _D]),
     "adi_factor": (_I, [_P, ctypes.c_double]),
+    "adi_set_pivot_floor": (_I, [_P, ctypes.c_double]),
     "adi_set_local_dt": (_I, [_P, _D]),
     "adi_set_source": (_I, [_P, _D, _I, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                             ctypes.c_double]),

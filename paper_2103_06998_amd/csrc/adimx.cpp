@@ -65,6 +65,7 @@ struct adi_ctx {
   double src_xs[3] = {0.5, 0.5, 0.5};
 
   double dt = 0.0, t = 0.0;
+  double pivot_floor = 1e-14;  // smallest accepted |U_rr| / |A_rr| of the LU
   bool factored = false;
 
   unsigned char* ws = nullptr;
@@ -795,6 +796,7 @@ int adi_factor(adi_ctx* c, double dt) {
   if (!c) return ADI_EINVAL;
   if (!c->have_material) return fail(c, ADI_ESTATE, "set the material before factor");
   if (!std::isfinite(dt) || dt < 0.0) return fail(c, ADI_EINVAL, "dt must be finite and >= 0");
+  c->factored = false;  // until this factorisation has succeeded
   int st = ensure_workspace(c);
   if (st != ADI_OK) return st;
   const int p = c->p, W = 2 * p + 1;
@@ -835,7 +837,8 @@ int adi_factor(adi_ctx* c, double dt) {
       if (v) apply_dirichlet(band, n, p);
       std::vector<double> L, U, Dinv;
       const double r = band_lu(band, n, p, L, U, Dinv);
-      if (!(r > 1e-14)) return fail(c, ADI_ESINGULAR, "singular mass matrix factor");
+      if (!(r > c->pivot_floor))
+        return fail(c, ADI_ESINGULAR, "pivot at or below the floor in a mass matrix factor");
       for (int i = 0; i < n; ++i)  // pre-scale the upper factor: D * U
         for (int k = 0; k < p; ++k) U[size_t(i) * p + k] *= Dinv[i];
       if ((st = upload(c, c->shL[ax][v], L)) != ADI_OK) return st;
@@ -929,11 +932,20 @@ int adi_factor(adi_ctx* c, double dt) {
       HIPCHK(c, hipStreamSynchronize(c->cap));
       for (double r : ratios) worst = std::min(worst, r);
     }
-  if (!(worst > 1e-14)) return fail(c, ADI_ESINGULAR, "tiny pivot in a material-modified factor");
+  if (!(worst > c->pivot_floor))
+    return fail(c, ADI_ESINGULAR, "pivot at or below the floor in a material-modified factor");
 
   st = capture(c);
   if (st != ADI_OK) return st;
   c->factored = true;
+  return ADI_OK;
+}
+
+int adi_set_pivot_floor(adi_ctx* c, double floor) {
+  if (!c) return ADI_EINVAL;
+  if (!std::isfinite(floor) || floor < 0.0) return fail(c, ADI_EINVAL, "pivot floor must be finite and >= 0");
+  c->pivot_floor = floor;
+  c->factored = false;
   return ADI_OK;
 }
 

@@ -107,6 +107,10 @@ class Solver:
         a = self._arr(np.broadcast_to(np.asarray(tau, float), self.shape), self.D)
         self._check(self.lib.adi_set_local_dt(self.h, _lib.dptr(a)))
 
+    def set_pivot_floor(self, floor: float):
+        """Smallest accepted pivot / diagonal ratio of the LU (default 1e-14)."""
+        self._check(self.lib.adi_set_pivot_floor(self.h, float(floor)))
+
     def factor(self, dt: float):
         self._check(self.lib.adi_factor(self.h, float(dt)))
 

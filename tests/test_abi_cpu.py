@@ -104,6 +104,9 @@ def test_host_validation_errors(lib):
         assert lib.adi_set_material_dof(h, d(one), d(one), d(np.zeros(D))) == _lib.ADI_OK
         assert lib.adi_factor(h, float("nan")) == _lib.ADI_EINVAL
         assert lib.adi_factor(h, -1.0) == _lib.ADI_EINVAL
+        assert lib.adi_set_pivot_floor(h, -1.0) == _lib.ADI_EINVAL
+        assert lib.adi_set_pivot_floor(h, float("inf")) == _lib.ADI_EINVAL
+        assert lib.adi_set_pivot_floor(h, 0.5) == _lib.ADI_OK
     finally:
         lib.adi_destroy(h)
 

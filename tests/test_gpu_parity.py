@@ -446,3 +446,34 @@ def test_shell32_subrun_50_steps(Solver, precision, tol):
     fields = {"E": rel_l2(got[:3], np.stack(E)), "H": rel_l2(got[3:], np.stack(H))}
     comp = compare_state(got, E, H, tol, ("shell32", precision))
     print("shell32", precision, "per-field relative L2:", fields, "per component:", comp)
+
+
+def test_singular_pivot_reported_and_context_usable(Solver):
+    """ADI_ESINGULAR: with the pivot floor raised above every pivot ratio of
+    the pivot-free LU (|U_rr| / |A_rr| <= 1 for these matrices) adi_factor
+    reports it; the context refuses to step and stays usable: with the
+    default floor it factors and steps as before.  (The shared mass factors
+    are checked first; adding alpha S with alpha >= 0 only raises the pivot
+    ratios of the material-modified factors, so their check cannot trip
+    before the shared one.)"""
+    from paper_2103_06998_amd import _lib
+    N, p = 6, 3
+    eps, mu, sig, src = random_setup(N, p, seed=31)
+    dt = 0.3
+    prob = maxwell.Problem(N, p, eps, mu, sig, dt, src)
+    s = make_gpu(Solver, N, p, eps, mu, sig, dt, src)
+    s.set_pivot_floor(2.0)
+    with pytest.raises(_lib.AdiError) as ei:
+        s.factor(dt)
+    assert ei.value.status == _lib.ADI_ESINGULAR
+    assert b"pivot" in s.lib.adi_last_error(s.h)
+    with pytest.raises(_lib.AdiError) as ei:
+        s.step(1)
+    assert ei.value.status == _lib.ADI_ESTATE
+    s.set_pivot_floor(1e-14)
+    s.factor(dt)
+    E, H = constrained_random_state(prob, 3)
+    s.set_fields(np.stack(E + H), 0.0)
+    s.step(2)
+    E, H, _ = prob.run(E, H, 0.0, 2)
+    compare_state(s.get_fields()[0], E, H, TOL64, "after ESINGULAR")
