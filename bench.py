@@ -80,7 +80,8 @@ def kernel_key(launch, nth, n, p, precision):
         stage = (8, 9)[sub] if k == "rhs_E" else (10, 11)[sub]
         return f"rhs_kernel<float, double, float, float, {p}, {stage}>"
     spike = 48 <= n <= 288 and launch["nmod"] == 0
-    MR = 40 if (n + 3) // 4 <= 40 else 72
+    m = (n + 3) // 4  # rows per segment of the partitioned solve
+    MR = next(r for r in (24, 36, 48, 72) if m <= r)
     mod = "true" if launch["nmod"] else "false"
     if k == "sweep_xyz":
         return f"spike_mixed_kernel<{T}, {p}, {MR}>" if spike else \

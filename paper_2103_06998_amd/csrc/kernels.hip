@@ -872,7 +872,8 @@ __device__ __forceinline__ void spike_body(const SweepArgs& a) {
   if (int(blockIdx.x) * 64 >= nl) return;  // block-uniform: before any barrier
   const int nf = n * (4 * P + 1) + Q * Q;
   T* gex = sf + nf;  // [Q][64] boundary values of g
-  const int tid = threadIdx.x, seg = tid >> 6, lane = tid & 63;
+  // the segment is the wave: wave-uniform, so its row offsets stay scalar
+  const int tid = threadIdx.x, seg = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const T* sL = sf;
   const T* sDU = sf + n * P;
   const T* sD = sf + 2 * n * P;
@@ -911,16 +912,17 @@ __device__ __forceinline__ void spike_body(const SweepArgs& a) {
   if (XAX && MR <= 40) {
     // short segments: every chunk's loads in flight at once (rows clamped),
     // then the chunks go through the tile one by one
-    T v[MR / 8][8];
+    constexpr int NC = (MR + 7) / 8;
+    T v[NC][8];
 #pragma unroll
-    for (int c = 0; c < MR / 8; ++c)
+    for (int c = 0; c < NC; ++c)
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         const int e = lane + 64 * j, ln = e >> 3, rr = e & 7;
         v[c][j] = in[size_t(min(l0 + ln, nl - 1)) * n + b0 + min(8 * c + rr, m - 1)];
       }
 #pragma unroll
-    for (int c = 0; c < MR / 8; ++c) {
+    for (int c = 0; c < NC; ++c) {
       if (8 * c < m) {  // uniform
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
@@ -929,7 +931,8 @@ __device__ __forceinline__ void spike_body(const SweepArgs& a) {
         }
         __builtin_amdgcn_wave_barrier();
 #pragma unroll
-        for (int rr = 0; rr < 8; ++rr) y[8 * c + rr] = xt[rr * 65 + lane];
+        for (int rr = 0; rr < 8; ++rr)
+          if (8 * c + rr < MR) y[8 * c + rr] = xt[rr * 65 + lane];
         __builtin_amdgcn_wave_barrier();
       }
     }
@@ -962,12 +965,22 @@ __device__ __forceinline__ void spike_body(const SweepArgs& a) {
   stage_batched<T, 64 * S>(sf, static_cast<const T*>(ds.spk), nf, tid);
   __syncthreads();  // factors staged
 
+  // Forward and backward recurrences over all MR rows without a branch per
+  // row, so that the compiler issues the factor reads of later rows (at
+  // fixed offsets from one base) ahead of the dependent arithmetic.  Rows
+  // r >= m (padding) read factors past the segment (the staged arrays are
+  // followed by others, so every read stays inside the block's LDS) and
+  // their results are never stored; in the backward pass they are set to
+  // zero, so the segment's last row starts from h = 0.  Long float64
+  // segments keep a branch per row: without it they need every register
+  // and ran slower (256^3, p = 2: 0.23 -> 0.31 ms per y/z launch).
+  constexpr bool kFlat = sizeof(T) * MR <= 8 * 48;
   T h[P];
 #pragma unroll
   for (int k = 0; k < P; ++k) h[k] = T(0);
 #pragma unroll
   for (int r = 0; r < MR; ++r) {
-    if (r < m) {  // uniform
+    if (kFlat || r < m) {  // compile-time, or wave-uniform
       const T* Lr = sL + (b0 + r) * P;
       T s = y[r];
 #pragma unroll
@@ -982,11 +995,12 @@ __device__ __forceinline__ void spike_body(const SweepArgs& a) {
   for (int k = 0; k < P; ++k) h[k] = T(0);
 #pragma unroll
   for (int r = MR - 1; r >= 0; --r) {
-    if (r < m) {
+    if (kFlat || r < m) {
       const int g = b0 + r;
       T s = sD[g] * y[r];
 #pragma unroll
       for (int k = P - 1; k >= 0; --k) s -= sDU[g * P + k] * h[k];
+      if (kFlat) s = (r < m) ? s : T(0);
 #pragma unroll
       for (int k = P - 1; k > 0; --k) h[k] = h[k - 1];
       h[0] = s;
@@ -1027,14 +1041,22 @@ __device__ __forceinline__ void spike_body(const SweepArgs& a) {
       up[k] = s;
     }
   }
+  // correction x = g - V T - W U in groups of four rows, each group behind a
+  // wave-uniform branch: the rows of a group read their spikes together,
+  // while the branches keep the compiler from holding every row's spikes in
+  // registers at once
+  constexpr int kGroup = kFlat ? 4 : 1;
 #pragma unroll
-  for (int r = 0; r < MR; ++r) {
-    if (r < m) {
-      const int g = b0 + r;
-      T x = y[r];
+  for (int r0 = 0; r0 < MR; r0 += kGroup) {
+    if (r0 < m) {  // uniform
 #pragma unroll
-      for (int k = 0; k < P; ++k) x -= sV[g * P + k] * tn[k] + sW[g * P + k] * up[k];
-      y[r] = x;
+      for (int r = r0; r < r0 + kGroup && r < MR; ++r) {
+        const int g = b0 + r;  // padding rows read past the segment, never stored
+        T x = y[r];
+#pragma unroll
+        for (int k = 0; k < P; ++k) x -= sV[g * P + k] * tn[k] + sW[g * P + k] * up[k];
+        y[r] = x;
+      }
     }
   }
   if (XAX) {
@@ -1059,12 +1081,16 @@ __device__ __forceinline__ void spike_body(const SweepArgs& a) {
       }
     }
   } else {
+    if (kFlat && accp) {  // uniform: the old state's rows (clamped, no branch per row)
+#pragma unroll
+      for (int r = 0; r < MR; ++r) y[r] += accp[lbase + size_t(b0 + min(r, m - 1)) * rstride];
+    }
 #pragma unroll
     for (int r = 0; r < MR; ++r) {
       if (r < m) {
         const size_t o = lbase + size_t(b0 + r) * rstride;
         T x = y[r];
-        if (accp) x += accp[o];
+        if (!kFlat && accp) x += accp[o];
         if (act) out[o] = x;
       }
     }
@@ -1298,12 +1324,23 @@ hipError_t launch_spike_mixed_k(int ndesc, const SweepArgs& a, hipStream_t s) {
 // xaxis: 0 = y/z lines, 1 = x lines, 2 = both (descriptor axis per block)
 template <typename T, int P>
 hipError_t launch_spike_x(int xaxis, int ndesc, const SweepArgs& a, hipStream_t s) {
-  // register rows per segment: ceil(n / kSpikeS) of the longest line
+  // register rows per segment: ceil(n / kSpikeS) of the longest line,
+  // rounded up to the nearest instantiated length (padding rows cost work)
   const int m = (launch_shape(ndesc, a).nmax + kSpikeS - 1) / kSpikeS;
-  if (m <= 40) {
-    if (xaxis == 2) return launch_spike_mixed_k<T, P, 40>(ndesc, a, s);
-    return xaxis ? launch_spike_k<T, P, true, 40>(ndesc, a, s)
-                 : launch_spike_k<T, P, false, 40>(ndesc, a, s);
+  if (m <= 24) {
+    if (xaxis == 2) return launch_spike_mixed_k<T, P, 24>(ndesc, a, s);
+    return xaxis ? launch_spike_k<T, P, true, 24>(ndesc, a, s)
+                 : launch_spike_k<T, P, false, 24>(ndesc, a, s);
+  }
+  if (m <= 36) {
+    if (xaxis == 2) return launch_spike_mixed_k<T, P, 36>(ndesc, a, s);
+    return xaxis ? launch_spike_k<T, P, true, 36>(ndesc, a, s)
+                 : launch_spike_k<T, P, false, 36>(ndesc, a, s);
+  }
+  if (m <= 48) {
+    if (xaxis == 2) return launch_spike_mixed_k<T, P, 48>(ndesc, a, s);
+    return xaxis ? launch_spike_k<T, P, true, 48>(ndesc, a, s)
+                 : launch_spike_k<T, P, false, 48>(ndesc, a, s);
   }
   if (m <= 72) {
     if (xaxis == 2) return launch_spike_mixed_k<T, P, 72>(ndesc, a, s);
