@@ -296,7 +296,10 @@ def test_conductivity_dissipates_energy():
 
 def test_appendix_toy_two_stage_solve():
     """Linear B-splines on [0 0 1 2 2]^2 with one eps per test function:
-    the two-stage solve (eq:split1, eq:split2) equals the 9x9 dense solve."""
+    the oracle's two-stage solve (eq:split1: per-line row-scaled systems
+    along x, then eq:split2: the shared mass matrix along y) equals the 9x9
+    dense solve of the row-scaled Kronecker system assembled here from
+    plain Gauss quadrature."""
     g = _golden("appendix_toy.json")
     knots = np.array(g["knots"], float)
     p = g["degree"]
@@ -307,6 +310,10 @@ def test_appendix_toy_two_stage_solve():
     V = bspline.basis(knots, p, pts)
     Mx = V.T @ (wts[:, None] * V)
     assert Mx.shape == (n, n)
+    # The oracle's Gram matrix lives on [0, 1]: twice it is the mass matrix
+    # on [0, 2] (two unit elements).
+    M01 = gram.gram_matrices(2, p)[0]
+    np.testing.assert_allclose(2.0 * M01, Mx, rtol=1e-14, atol=1e-15)
     rng = np.random.default_rng(9)
     eps = rng.uniform(1, 10, (n, n))  # eps[r, s]: test function B_r(x) B_s(y)
     F = rng.standard_normal((n, n))   # F[r, s] = (F, B_r B_s)
@@ -318,10 +325,15 @@ def test_appendix_toy_two_stage_solve():
                 for j in range(n):
                     G[r * n + s, i * n + j] = eps[r, s] * Mx[r, i] * Mx[s, j]
     u_dense = np.linalg.solve(G, F.ravel()).reshape(n, n)
-    # two stages: A_s = diag(eps[:, s]) Mx ; G_s = A_s^-1 F_s ; My U^T = G^T
-    Gs = np.stack([np.linalg.solve(eps[:, s][:, None] * Mx, F[:, s]) for s in range(n)], axis=1)
-    U = np.linalg.solve(Mx, Gs.T).T
+    # Stage 1: line s along x solves diag(eps[:, s]) Mx (rows scaled, the
+    # base matrix zero); stage 2: the unmodified Mx along y.
+    stage1 = banded.solve_axis(F, 0, np.zeros((n, n)), p, stiff=Mx, alpha=eps)
+    U = banded.solve_axis(stage1, 1, Mx, p)
     np.testing.assert_allclose(U, u_dense, rtol=1e-13, atol=1e-14)
+    # The literal order (shared matrix first) is a different operator.
+    W = banded.solve_axis(banded.solve_axis(F, 1, Mx, p), 0, np.zeros((n, n)), p,
+                          stiff=Mx, alpha=eps)
+    assert np.max(np.abs(W - u_dense)) > 1e-3 * np.max(np.abs(u_dense))
 
 
 def test_pivot_free_lu_on_strong_material_jump():
@@ -336,3 +348,31 @@ def test_pivot_free_lu_on_strong_material_jump():
     L, U = banded.band_lu(band, p)
     assert banded.min_pivot_ratio(U, band, p) > 0.5
     assert np.abs(L).max() < 1.0
+
+
+def _shell(N, p):
+    """Nested boxes around the centre: 1 | 15 | 50 (air, skull-like shell,
+    tissue-like core), at the Greville points."""
+    xi = bspline.greville(bspline.open_uniform_knots(N, p), p)
+    Z, Y, X = np.meshgrid(xi, xi, xi, indexing="ij")
+    r = np.maximum(np.maximum(np.abs(X - 0.5), np.abs(Y - 0.5)), np.abs(Z - 0.5))
+    return np.where(r < 0.2, 50.0, np.where(r < 0.34, 15.0, 1.0))
+
+
+@pytest.mark.slow
+def test_stability_range_with_material_jumps():
+    """The scheme's stability with test-function-wise material, mapped by the
+    spectral radius of the step matrix (sigma = 0, J = 0; shell-like 1 | 15 |
+    50 jumps, 4^3 elements, p = 2): no growth up to tau = 2h (the coarse step
+    of the learned closure), growth at tau = 4h.  With constant material the
+    scheme is unconditionally stable (test above); the paper's claim does not
+    carry over to per-row material at every step size."""
+    N, p = 4, 2
+    eps = _shell(N, p)
+    for tau_over_h, stable in ((1.0, True), (2.0, True), (4.0, False)):
+        prob = maxwell.Problem(N, p, eps, 1.0, 0.0, tau_over_h / N)
+        rho = np.abs(np.linalg.eigvals(_step_matrix(prob))).max()
+        if stable:
+            assert rho <= 1.0 + 1e-12, (tau_over_h, rho)
+        else:
+            assert rho > 1.0 + 1e-3, (tau_over_h, rho)
