@@ -66,10 +66,15 @@ def algorithmic_bytes(launch, D, wbytes):
     return D * wbytes * (2 * launch["ncomp"] + launch["nmod"] + launch.get("nacc", 0))
 
 
-def kernel_key(launch, nth, n, p, precision):
+RES64_DEFAULT = 4  # float32 mode: the E stage of substep 2 forms its increment in float64
+
+
+def kernel_key(launch, nth, n, p, precision, res64=RES64_DEFAULT):
     """Name of the HIP kernel a profiled launch ran (as rocprofv3 reports it,
     without namespace and arguments); nth = index among launches of its kind
-    in the step (right-hand sides: 0 = substep 1, 1 = substep 2)."""
+    in the step (right-hand sides: 0 = substep 1, 1 = substep 2); res64 =
+    the float32 mode's mask of stages whose increment uses float64
+    arithmetic (bit 2 (sub - 1) + (0 for E, 1 for H))."""
     k = launch["kind"]
     T = "double" if precision == "fp64" else "float"
     if k in ("rhs_E", "rhs_H"):
@@ -78,7 +83,9 @@ def kernel_key(launch, nth, n, p, precision):
             stage = (0, 1)[sub] if k == "rhs_E" else (2, 3)[sub]
             return f"rhs_kernel<double, double, double, double, {p}, {stage}>"
         stage = (8, 9)[sub] if k == "rhs_E" else (10, 11)[sub]
-        return f"rhs_kernel<float, double, float, float, {p}, {stage}>"
+        bit = 1 << (2 * sub + (0 if k == "rhs_E" else 1))
+        TC = "double" if res64 & bit else "float"
+        return f"rhs_kernel<float, {TC}, float, float, {p}, {stage}>"
     spike = 48 <= n <= 288 and launch["nmod"] == 0
     m = (n + 3) // 4  # rows per segment of the partitioned solve
     MR = next(r for r in (24, 36, 48, 72) if m <= r)
@@ -91,14 +98,14 @@ def kernel_key(launch, nth, n, p, precision):
         f"sweep_kernel<{T}, {p}, {xax}, {mod}>"
 
 
-def summarize(launches, D, n, p, precision):
+def summarize(launches, D, n, p, precision, res64=RES64_DEFAULT):
     """Per kernel: launches per step, total and mean duration, algorithmic bytes."""
     wbytes = 8 if precision == "fp64" else 4
     by, seen = {}, {}
     for L in launches:
         nth = seen.get(L["kind"], 0)
         seen[L["kind"]] = nth + 1
-        key = kernel_key(L, nth, n, p, precision)
+        key = kernel_key(L, nth, n, p, precision, res64)
         b = by.setdefault(key, dict(total_ms=0.0, launches=0, bytes=0.0, factor_bytes=0.0))
         b["total_ms"] += L["ms"]
         b["launches"] += 1
@@ -134,7 +141,7 @@ def traffic_from_profiles(key, precision):
 MODEL_WORDS_PER_STEP = 130
 
 
-def run_gpu(precision, w, steps, warmup):
+def run_gpu(precision, w, steps, warmup, res64=RES64_DEFAULT):
     import torch
     from paper_2103_06998_amd.solver import Solver
 
@@ -145,6 +152,7 @@ def run_gpu(precision, w, steps, warmup):
     s.set_material(m.eps_r, m.mu_r, m.sigma_nd)
     src = w.source
     s.set_source(src.xs, src.comp, src.amp, src.f0, src.t0, src.width)
+    s.set_residual64(res64)
     s.factor(w.dt)
     s.set_fields(np.zeros((6, n, n, n)), 0.0)
     s.step(warmup)
@@ -160,7 +168,7 @@ def run_gpu(precision, w, steps, warmup):
     s.profile(max(5, min(steps, 50)))
     launches = s.profile_read()
     wbytes = 8 if precision == "fp64" else 4
-    kernels = summarize(launches, D, n, w.p, precision)
+    kernels = summarize(launches, D, n, w.p, precision, res64)
     EH, t = s.get_fields()
     finite = bool(np.isfinite(EH).all())
     s.close()
@@ -268,8 +276,16 @@ def main():
     log(f"workload shell128: N={w.N} p={w.p} n={n} dt={w.dt}")
     res32 = run_gpu("fp32_refine", w, args.steps, args.warmup)
     log(f"fp32_refine: {res32['ms_per_step']:.3f} ms/step {res32['value']:.3e} DOF/s")
-    res64 = run_gpu("fp64", w, args.steps, args.warmup)
-    log(f"fp64: {res64['ms_per_step']:.3f} ms/step {res64['value']:.3e} DOF/s")
+    r64 = run_gpu("fp64", w, args.steps, args.warmup)
+    log(f"fp64: {r64['ms_per_step']:.3f} ms/step {r64['value']:.3e} DOF/s")
+    # the float32 mode with its increments in float32 arithmetic everywhere
+    # (mask 0) and in float64 for every stage (mask 15), beside the default
+    residual = {}
+    for mask in (0, 15):
+        r = run_gpu("fp32_refine", w, args.steps, args.warmup, mask)
+        log(f"fp32_refine, float64 increments mask {mask}: {r['ms_per_step']:.3f} ms/step")
+        residual[str(mask)] = {"ms_per_step": r["ms_per_step"], "value": r["value"],
+                               "finite": r["finite"]}
     big = None
     if not args.no_256:
         w4 = workloads.make("shell256")
@@ -298,20 +314,24 @@ def main():
         "data": "synthetic",
         "config": {"workload": "shell128: 128^3 elements, p=3, n=131 coefficients per axis, "
                                "256^3 ellipsoidal-shell voxel map (seed 3), dipole in air at "
-                               "(0.5,0.5,0.04), dt=1/256, float32 state and sweeps, factors "
-                               "computed in float64, every stage solved in increment form "
-                               "from a float64 residual of the old state",
+                               "(0.5,0.5,0.04), dt=1/256, float32 state, right-hand sides and "
+                               "sweeps with float32 accumulation, factors computed in float64, "
+                               "every stage solved in increment form (residual correction of "
+                               "the old state), the residual of the E stage that closes each "
+                               "step formed in float64 arithmetic",
+                   "res64_mask": RES64_DEFAULT,
                    "N": w.N, "p": w.p, "dofs": 6 * n ** 3},
         "roofline": res32["roofline"],
         "cpu_baseline": cpu,
         "step_frac_hbm": res32["step_frac_hbm"],
         "step_bytes": res32["step_bytes"],
         "kernels": res32["kernels"],
-        "fp64": {"value": res64["value"], "ms_per_step": res64["ms_per_step"], "dtype": "f64",
-                 "roofline": res64["roofline"], "step_frac_hbm": res64["step_frac_hbm"],
-                 "step_bytes": res64["step_bytes"], "kernels": res64["kernels"],
-                 "finite": res64["finite"]},
+        "fp64": {"value": r64["value"], "ms_per_step": r64["ms_per_step"], "dtype": "f64",
+                 "roofline": r64["roofline"], "step_frac_hbm": r64["step_frac_hbm"],
+                 "step_bytes": r64["step_bytes"], "kernels": r64["kernels"],
+                 "finite": r64["finite"]},
         "finite": res32["finite"],
+        "fp32_residual_masks": residual,
         "shell256": big,
     }
     print(json.dumps(out), flush=True)

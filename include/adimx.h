@@ -49,12 +49,25 @@ enum {
 
 enum {
   ADI_FP64 = 0,        /* fields, right-hand sides and sweeps in float64     */
-  ADI_FP32_REFINE = 1  /* float32 state and sweeps, factors computed in
-                          float64; every stage solved in increment form: its
+  ADI_FP32_REFINE = 1  /* float32 state, right-hand sides and sweeps with
+                          float32 accumulation, factors computed in float64;
+                          every stage solved in increment form: its
                           right-hand-side kernel forms the residual of the old
-                          state, b - P x_old, in float64 arithmetic, the
-                          float32 sweeps solve P d = b - P x_old and the last
-                          sweep stores x_old + d                               */
+                          state, b - P x_old, the float32 sweeps solve
+                          P d = b - P x_old and the last sweep stores
+                          x_old + d.  The residual of the stages selected by
+                          adi_set_residual64 (default: the E stage of
+                          substep 2, once per step) is formed in float64
+                          arithmetic                                          */
+};
+
+/* adi_set_residual64 mask bits: stage E / H of substep 1 / 2 */
+enum {
+  ADI_RES64_E1 = 1,
+  ADI_RES64_H1 = 2,
+  ADI_RES64_E2 = 4,
+  ADI_RES64_H2 = 8,
+  ADI_RES64_DEFAULT = ADI_RES64_E2
 };
 
 enum {
@@ -135,6 +148,19 @@ int adi_factor(adi_ctx* ctx, double dt);
  * effect at the next adi_factor.
  */
 int adi_set_pivot_floor(adi_ctx* ctx, double floor);
+
+/*
+ * ADI_FP32_REFINE mode: the stages whose increment b - P x_old is formed in
+ * float64 arithmetic (an OR of ADI_RES64_* bits, 0..15; the rest use
+ * float32 arithmetic and accumulation).  The increment form is the
+ * residual correction of each stage's float32 solve of the three 1D
+ * systems of section "Incorporating non-regular material data" (the
+ * precision split is this library's, not the paper's).  Default
+ * ADI_RES64_DEFAULT.
+ * Ignored in ADI_FP64 mode.  Takes effect at the next adi_factor (the
+ * context is unfactored until then).  EINVAL for a mask outside 0..15.
+ */
+int adi_set_residual64(adi_ctx* ctx, int mask);
 
 /*
  * Point dipole source J = amp g(t) e_comp delta(x - xs) with
@@ -340,10 +366,12 @@ int adi_closure_apply(adi_ctx* ctx, const float* y_dev, const float* scale_dev);
 /*
  * nsteps closure steps on the context's stream: mark, one ADI step, features,
  * network forward, apply.  nn must map 16 features to 6 outputs and must not
- * be used on another stream meanwhile.  gate > 0 skips a correction whose
- * RMS (in units of s) exceeds gate -- that step stays a plain
- * ADI step -- and counts it (adi_closure_rejected, which waits); gate <= 0
- * applies every one.
+ * be used on another stream meanwhile.  gate > 0 judges each correction
+ * against the coarse step it corrects: a correction whose RMS exceeds gate
+ * times the RMS of that step's change (state after minus state before the
+ * step) is skipped -- that step stays a plain ADI step -- and counted
+ * (adi_closure_rejected, which waits); so a step that changed nothing takes
+ * no correction.  gate <= 0 applies every one.
  */
 int adi_step_closure(adi_ctx* ctx, adi_nn* nn, int nsteps, float gate);
 int adi_closure_rejected(adi_ctx* ctx, int* count);

@@ -15,6 +15,8 @@ ADI_OK, ADI_EINVAL, ADI_ENOMEM, ADI_EHIP, ADI_ESINGULAR, ADI_ENONFINITE, ADI_EST
     0, -1, -2, -3, -4, -5, -6
 ADI_FP64, ADI_FP32_REFINE = 0, 1
 ADI_MAP_GREVILLE, ADI_MAP_BSPLINE_AVG = 0, 1
+ADI_RES64_E1, ADI_RES64_H1, ADI_RES64_E2, ADI_RES64_H2 = 1, 2, 4, 8
+ADI_RES64_DEFAULT = ADI_RES64_E2
 
 STATUS_NAMES = {0: "ADI_OK", -1: "ADI_EINVAL", -2: "ADI_ENOMEM", -3: "ADI_EHIP",
                 -4: "ADI_ESINGULAR", -5: "ADI_ENONFINITE", -6: "ADI_ESTATE"}
@@ -34,6 +36,7 @@ SIGNATURES = {
     "adi_set_material_dof": (_I, [_P, _D, _D, _D]),
     "adi_factor": (_I, [_P, ctypes.c_double]),
     "adi_set_pivot_floor": (_I, [_P, ctypes.c_double]),
+    "adi_set_residual64": (_I, [_P, _I]),
     "adi_set_local_dt": (_I, [_P, _D]),
     "adi_set_source": (_I, [_P, _D, _I, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                             ctypes.c_double]),

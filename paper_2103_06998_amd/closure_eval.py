@@ -6,9 +6,12 @@
 Training: 64^3 elements of degree train-p on three-class blob maps (seeds
 100, 101, ...), a dipole at a random position per map; pairs are one ADI
 step of 4 h_t against four steps of h_t = 1/(2N) from states along a fine
-trajectory.  Evaluation: 128^3 elements, p = 3, unseen nested-shell maps,
-the dipole of the shell workload, 200 steps of h_t = 1/256 for plain ADI
-against 50 closure steps of 4 h_t, every run against float64 ADI at h_t / 4.
+trajectory.  Evaluation (--eval shell128): 128^3 elements, p = 3, unseen
+nested-shell maps, the dipole of the shell workload, 200 steps of
+h_t = 1/256 for plain ADI against 50 closure steps of 4 h_t, every run
+against float64 ADI at h_t / 4; --eval blob: in distribution, on unseen blob
+maps and dipoles at the training grid, degree and h_t.  The gate judges each
+correction against the coarse step's change (adi_step_closure).
 Prints one JSON object per evaluation map and a summary line.
 """
 from __future__ import annotations
@@ -33,7 +36,8 @@ def main(argv=None):
     ap.add_argument("--pairs-per-map", type=int, default=32)
     ap.add_argument("--iters", type=int, default=8000)
     ap.add_argument("--lr", type=float, default=2e-3)
-    ap.add_argument("--gate", type=float, default=1.0)
+    ap.add_argument("--gate", type=float, default=0.5)
+    ap.add_argument("--eval", choices=("shell128", "blob"), default="shell128")
     ap.add_argument("--eval-seeds", type=int, nargs="*", default=[9001, 9002, 9003])
     ap.add_argument("--save", default="")
     args = ap.parse_args(argv)
@@ -81,16 +85,19 @@ def main(argv=None):
     wl = workloads.make("shell128")
     rows = []
     for seed in args.eval_seeds:
-        mat = workloads.shell_map(256, seed)
-        res = closure.run_comparison(128, 3, mat, wl.source, 1.0 / 256, 200, net,
-                                     gate=args.gate, time_reps=2)
+        if args.eval == "shell128":
+            res = closure.run_comparison(128, 3, workloads.shell_map(256, seed), wl.source,
+                                         1.0 / 256, 200, net, gate=args.gate, time_reps=2)
+        else:
+            res = closure.run_comparison(N, p, workloads.blob_map(N, seed), train_source(seed),
+                                         h_t, 200, net, gate=args.gate, time_reps=2)
         row = dict(seed=seed, fine_err=res["fine"]["rel_l2"], coarse_err=res["coarse"]["rel_l2"],
                    closure_err=res["closure"]["rel_l2"], fine_ms=res["fine"]["ms"],
                    coarse_ms=res["coarse"]["ms"], closure_ms=res["closure"]["ms"],
                    rejected=res.get("rejected", 0), speedup_vs_fine=res["speedup_vs_fine"])
         rows.append(row)
         log(json.dumps(row))
-    summary = dict(train_p=p, train_N=N, pairs=len(pairs.x), iters=args.iters,
+    summary = dict(eval=args.eval, train_p=p, train_N=N, pairs=len(pairs.x), iters=args.iters,
                    train_s=round(train_s, 2), pair_gen_s=round(gen_s, 2),
                    held_one_step_ratio=round(held_ratio, 4), gate=args.gate,
                    mean_fine_err=float(np.mean([r["fine_err"] for r in rows])),

@@ -9,10 +9,12 @@
 //            exactly; the remaining two axes have shared factors);
 //   H stage: right-hand sides of H1, H2, H3, then mass solves along x, y, z.
 // In ADI_FP32_REFINE mode every stage is solved in increment form: the
-// right-hand-side kernel forms b - P x_old in float64 arithmetic from the
-// float32 state (the residual of the old state), the float32 sweeps solve
-// P d = b - P x_old, and the last sweep adds x_old, so the float32 solve's
-// rounding scales with the increment d instead of with the state.
+// right-hand-side kernel forms b - P x_old from the float32 state (the
+// residual of the old state; float32 arithmetic, or float64 for the stages
+// selected by adi_set_residual64, by default the E stage of substep 2), the
+// float32 sweeps solve P d = b - P x_old, and the last sweep adds x_old, so
+// the float32 solve's rounding scales with the increment d instead of with
+// the state.
 #include "adimx.h"
 #include "adimx_internal.h"
 #include "closure_internal.h"
@@ -66,6 +68,9 @@ struct adi_ctx {
 
   double dt = 0.0, t = 0.0;
   double pivot_floor = 1e-14;  // smallest accepted |U_rr| / |A_rr| of the LU
+  // float32 mode: stages whose increment is formed in float64 arithmetic
+  // (bit res64_bit(stage, sub)); the others use float32 arithmetic
+  int res64 = ADI_RES64_DEFAULT;
   bool factored = false;
 
   unsigned char* ws = nullptr;
@@ -120,6 +125,9 @@ struct adi_ctx {
 };
 
 namespace {
+
+// Bit of adi_set_residual64's mask for stage 0 = E, 1 = H of substep sub.
+constexpr int res64_bit(int stage, int sub) { return 1 << (2 * (sub - 1) + stage); }
 
 int fail(adi_ctx* c, int code, const std::string& msg) {
   if (c) c->err = msg;
@@ -454,14 +462,19 @@ hipError_t enqueue_step_t(adi_ctx* c, hipStream_t s) {
           return launch_rhs<T>(sub == 1 ? kStageE1 : kStageE2, c->p, a, s);
         });
       } else {
-        RhsArgs<double> a = rhs_args<double>(c, f, 6, out, 0, sub);
-        a.coef[0] = c->gm1T;  // gamma - 1: the mass part of P E folded in
-        a.bandx = c->band64[0];
-        a.bandy = c->band64[1];
-        a.zw = c->zw64;
-        e = timed(c, s, kKindRhsE, 3, 0, 0, [&] {
-          return launch_rhs_inc(sub == 1 ? kStageEd1 : kStageEd2, c->p, a, s);
-        });
+        const int stage = sub == 1 ? kStageEd1 : kStageEd2;
+        if (c->res64 & res64_bit(0, sub)) {
+          RhsArgs<double> a = rhs_args<double>(c, f, 6, out, 0, sub);
+          a.coef[0] = c->gm1T;  // gamma - 1: the mass part of P E folded in
+          a.bandx = c->band64[0];
+          a.bandy = c->band64[1];
+          a.zw = c->zw64;
+          e = timed(c, s, kKindRhsE, 3, 0, 0, [&] { return launch_rhs_inc(stage, c->p, a, s); });
+        } else {
+          RhsArgs<float> a = rhs_args<float>(c, f, 6, out, 0, sub);
+          a.coef[0] = c->gm1T;
+          e = timed(c, s, kKindRhsE, 3, 0, 0, [&] { return launch_rhs_inc32(stage, c->p, a, s); });
+        }
       }
       if (e != hipSuccess) return e;
       e = enqueue_solves<T>(c, 0, sub, Eout, c->refine() ? Ein : nullptr, s);
@@ -481,13 +494,17 @@ hipError_t enqueue_step_t(adi_ctx* c, hipStream_t s) {
         });
       } else {
         // increments b - M H_old: the delta terms alone (H_old is not read)
-        RhsArgs<double> a = rhs_args<double>(c, f, 9, out, 1, sub);
-        a.bandx = c->band64[0];
-        a.bandy = c->band64[1];
-        a.zw = c->zw64;
-        e = timed(c, s, kKindRhsH, 3, 0, 0, [&] {
-          return launch_rhs_inc(sub == 1 ? kStageHd1 : kStageHd2, c->p, a, s);
-        });
+        const int stage = sub == 1 ? kStageHd1 : kStageHd2;
+        if (c->res64 & res64_bit(1, sub)) {
+          RhsArgs<double> a = rhs_args<double>(c, f, 9, out, 1, sub);
+          a.bandx = c->band64[0];
+          a.bandy = c->band64[1];
+          a.zw = c->zw64;
+          e = timed(c, s, kKindRhsH, 3, 0, 0, [&] { return launch_rhs_inc(stage, c->p, a, s); });
+        } else {
+          RhsArgs<float> a = rhs_args<float>(c, f, 9, out, 1, sub);
+          e = timed(c, s, kKindRhsH, 3, 0, 0, [&] { return launch_rhs_inc32(stage, c->p, a, s); });
+        }
       }
       if (e != hipSuccess) return e;
       // H: x, y, z (all shared factors); the last launch advances the time
@@ -949,6 +966,14 @@ int adi_set_pivot_floor(adi_ctx* c, double floor) {
   return ADI_OK;
 }
 
+int adi_set_residual64(adi_ctx* c, int mask) {
+  if (!c) return ADI_EINVAL;
+  if (mask < 0 || mask > 15) return fail(c, ADI_EINVAL, "residual mask must be in [0, 15]");
+  c->res64 = mask;
+  c->factored = false;  // the captured step changes
+  return ADI_OK;
+}
+
 int adi_set_fields(adi_ctx* c, const double* EH, double t) {
   if (!c || !EH) return ADI_EINVAL;
   if (!finite_all(EH, 6 * c->D) || !std::isfinite(t))
@@ -1306,8 +1331,17 @@ int adi_step_closure(adi_ctx* c, adi_nn* nn_, int nsteps, float gate) {
     if (st != ADI_OK) return fail(c, st, "network forward");
     const int* flag = nullptr;
     if (gate > 0.f) {
-      HIPCHK(c, nn::launch_gate(y, c->D * nn::kOutputs, partial, kClosureBlocks, gate, c->cl_flag,
-                                c->cl_flag + 1, c->stream));
+      const size_t count = c->D * nn::kOutputs;
+      if (c->esz == 8)
+        HIPCHK(c, nn::launch_gate<double>(y, static_cast<const double*>(c->B[0]),
+                                          static_cast<const double*>(c->cl_prev), count, partial,
+                                          kClosureBlocks, scale, gate, c->cl_flag, c->cl_flag + 1,
+                                          c->stream));
+      else
+        HIPCHK(c, nn::launch_gate<float>(y, static_cast<const float*>(c->B[0]),
+                                         static_cast<const float*>(c->cl_prev), count, partial,
+                                         kClosureBlocks, scale, gate, c->cl_flag, c->cl_flag + 1,
+                                         c->stream));
       flag = c->cl_flag;
     }
     HIPCHK(c, enqueue_apply(c, y, scale, flag));

@@ -134,6 +134,8 @@ hipError_t launch_rhs(int stage, int p, const RhsArgs<T>& a, hipStream_t stream)
 // coefficients, float64 arithmetic (bands and z weights in float64), float32
 // outputs.
 hipError_t launch_rhs_inc(int stage, int p, const RhsArgs<double>& a, hipStream_t stream);
+// The same increments in float32 arithmetic and accumulation (float32 bands).
+hipError_t launch_rhs_inc32(int stage, int p, const RhsArgs<float>& a, hipStream_t stream);
 template <typename T>
 hipError_t launch_sweep(int p, int ndesc, const SweepArgs& a, hipStream_t stream);
 hipError_t launch_factor(int p, const FactorArgs& a, hipStream_t stream);

@@ -202,13 +202,23 @@ __global__ __launch_bounds__(kThreads) void wgrad_kernel(WgradArgs a) {
   }
 }
 
-// Sum the per-block partials (fixed order: deterministic) into the gradient
-// in the master layout W[t][ci][co] (ci < cin, co < cout), then b[co].
-__global__ void wgrad_reduce_kernel(const float* __restrict__ part, int nblk, int CI, int COP,
-                                    int cin, int cout, float* __restrict__ grad) {
+// Sum the per-block partials into the gradient in the master layout
+// W[t][ci][co] (ci < cin, co < cout), then b[co].  A block owns 64 outputs;
+// its four waves each sum every fourth partial (b = wave, wave + 4, ...) in
+// increasing b, and the four sums are added in wave order: a fixed order, so
+// the result is bitwise repeatable, with 4x the loads in flight of one
+// serial sum per output.
+constexpr int kReduceOut = 64, kReduceSplit = 4;
+__global__ void __launch_bounds__(kReduceOut * kReduceSplit)
+wgrad_reduce_kernel(const float* __restrict__ part, int nblk, int CI, int COP, int cin, int cout,
+                    float* __restrict__ grad) {
+  __shared__ float acc[kReduceSplit][kReduceOut];
   const int nW = 27 * cin * cout;
   const size_t stride = size_t(27) * CI * COP + COP;
-  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < nW + cout; j += gridDim.x * blockDim.x) {
+  const int lane = threadIdx.x % kReduceOut, g = threadIdx.x / kReduceOut;
+  const int j = blockIdx.x * kReduceOut + lane;
+  float s = 0.f;
+  if (j < nW + cout) {
     size_t src;
     if (j < nW) {
       const int t = j / (cin * cout), rem = j % (cin * cout), ci = rem / cout, co = rem % cout;
@@ -216,9 +226,26 @@ __global__ void wgrad_reduce_kernel(const float* __restrict__ part, int nblk, in
     } else {
       src = size_t(27) * CI * COP + (j - nW);
     }
-    float s = 0.f;
-    for (int b = 0; b < nblk; ++b) s += part[b * stride + src];
-    grad[j] = s;
+    const float* q = part + src;
+    int b = g;
+    for (; b + 3 * kReduceSplit < nblk; b += 4 * kReduceSplit) {
+      const float v0 = q[size_t(b) * stride], v1 = q[size_t(b + kReduceSplit) * stride],
+                  v2 = q[size_t(b + 2 * kReduceSplit) * stride],
+                  v3 = q[size_t(b + 3 * kReduceSplit) * stride];
+      s += v0;
+      s += v1;
+      s += v2;
+      s += v3;
+    }
+    for (; b < nblk; b += kReduceSplit) s += q[size_t(b) * stride];
+  }
+  acc[g][lane] = s;
+  __syncthreads();
+  if (g == 0 && j < nW + cout) {
+    float r = acc[0][lane];
+#pragma unroll
+    for (int w = 1; w < kReduceSplit; ++w) r += acc[w][lane];
+    grad[j] = r;
   }
 }
 
@@ -324,8 +351,8 @@ hipError_t launch_wgrad(int ci, int cop, const WgradArgs& a, int cin, int cout, 
   if (e != hipSuccess) return e;
   const int nblk = int(grid.x * grid.y * grid.z);
   const int n = 27 * cin * cout + cout;
-  hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((n + 255) / 256), dim3(256), 0, s, a.part, nblk, ci,
-                     cop, cin, cout, grad);
+  hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((n + kReduceOut - 1) / kReduceOut),
+                     dim3(kReduceOut * kReduceSplit), 0, s, a.part, nblk, ci, cop, cin, cout, grad);
   return hipGetLastError();
 }
 
@@ -485,12 +512,41 @@ __global__ void apply_kernel(T* __restrict__ state, int n, const float* __restri
   }
 }
 
-// Gate of the correction: flag = (RMS of y > limit); counts rejections.
-__global__ void gate_kernel(const float* __restrict__ partial, int nblk, size_t count, float limit,
+// Per-block sums of squares of the change a - b (the coarse step's change
+// C - S when a is the state after the step and b the marked state before).
+template <typename T>
+__global__ void diffsq_kernel(const T* __restrict__ a, const T* __restrict__ b, size_t count,
+                              float* __restrict__ partial) {
+  __shared__ float red[256];
+  double s = 0.0;
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < count;
+       i += size_t(gridDim.x) * blockDim.x) {
+    const double v = double(a[i]) - double(b[i]);
+    s += v * v;
+  }
+  red[threadIdx.x] = float(s);
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+// Gate of the correction, judged against the coarse step it corrects: the
+// correction s * y is rejected (flag set, counter raised) when its RMS
+// exceeds limit times the RMS of the step's change C - S.  A step that
+// changed nothing (a zero state without a source) therefore takes no
+// correction at all.
+__global__ void gate_kernel(const float* __restrict__ partial_y, const float* __restrict__ partial_d,
+                            int nblk, size_t count, const float* __restrict__ scale, float limit,
                             int* __restrict__ flag, int* __restrict__ rejected) {
-  const float r = rms_of_partials(partial, nblk, count);
+  const float ry = rms_of_partials(partial_y, nblk, count);
+  __syncthreads();
+  const float rd = rms_of_partials(partial_d, nblk, count);
   if (threadIdx.x == 0) {
-    const int bad = !(r <= limit);  // NaN counts as out of range
+    const float corr = scale[0] * ry;
+    const int bad = !(corr <= limit * rd);  // NaN counts as out of range
     flag[0] = bad;
     if (bad) rejected[0] += 1;
   }
@@ -535,11 +591,15 @@ hipError_t launch_apply(T* state, int n, const float* y, const float* scale, con
   return hipGetLastError();
 }
 
-hipError_t launch_gate(const float* y, size_t count, float* partial, int nblk, float limit,
-                       int* flag, int* rejected, hipStream_t s) {
+template <typename T>
+hipError_t launch_gate(const float* y, const T* state, const T* prev, size_t count, float* partial,
+                       int nblk, const float* scale, float limit, int* flag, int* rejected,
+                       hipStream_t s) {
   hipLaunchKernelGGL(sumsq_kernel<float>, dim3(nblk), dim3(256), 0, s, y, count, partial);
-  hipLaunchKernelGGL(gate_kernel, dim3(1), dim3(256), 0, s, partial, nblk, count, limit, flag,
-                     rejected);
+  hipLaunchKernelGGL(diffsq_kernel<T>, dim3(nblk), dim3(256), 0, s, state, prev, count,
+                     partial + nblk);
+  hipLaunchKernelGGL(gate_kernel, dim3(1), dim3(256), 0, s, partial, partial + nblk, nblk, count,
+                     scale, limit, flag, rejected);
   return hipGetLastError();
 }
 
@@ -551,7 +611,9 @@ hipError_t launch_gate(const float* y, size_t count, float* partial, int nblk, f
   template hipError_t launch_target<T>(const T*, const T*, size_t, const float*, float*,          \
                                        hipStream_t);                                              \
   template hipError_t launch_apply<T>(T*, int, const float*, const float*, const int*,            \
-                                      hipStream_t);
+                                      hipStream_t);                                               \
+  template hipError_t launch_gate<T>(const float*, const T*, const T*, size_t, float*, int,        \
+                                     const float*, float, int*, int*, hipStream_t);
 INST(double)
 INST(float)
 #undef INST

@@ -57,8 +57,12 @@ hipError_t launch_target(const T* fine, const T* coarse, size_t D, const float* 
 template <typename T>
 hipError_t launch_apply(T* state, int n, const float* y, const float* scale, const int* flag,
                         hipStream_t s);
-hipError_t launch_gate(const float* y, size_t count, float* partial, int nblk, float limit,
-                       int* flag, int* rejected, hipStream_t s);
+// Gate: flag = (RMS of scale * y > limit * RMS of state - prev); partial
+// holds 2 nblk floats.
+template <typename T>
+hipError_t launch_gate(const float* y, const T* state, const T* prev, size_t count, float* partial,
+                       int nblk, const float* scale, float limit, int* flag, int* rejected,
+                       hipStream_t s);
 
 }  // namespace nn
 }  // namespace adimx

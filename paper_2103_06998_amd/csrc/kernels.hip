@@ -1388,6 +1388,28 @@ hipError_t launch_rhs(int stage, int p, const RhsArgs<T>& a, hipStream_t s) {
 template hipError_t launch_rhs<double>(int, int, const RhsArgs<double>&, hipStream_t);
 template hipError_t launch_rhs<float>(int, int, const RhsArgs<float>&, hipStream_t);
 
+template <int P>
+hipError_t launch_inc32_p(int stage, const RhsArgs<float>& a, hipStream_t s) {
+  switch (stage) {
+    case kStageEd1: return launch_rhs_t<float, float, float, float, P, kStageEd1>(a, s);
+    case kStageEd2: return launch_rhs_t<float, float, float, float, P, kStageEd2>(a, s);
+    case kStageHd1: return launch_rhs_t<float, float, float, float, P, kStageHd1>(a, s);
+    case kStageHd2: return launch_rhs_t<float, float, float, float, P, kStageHd2>(a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+// Increments of the float32 mode in float32 arithmetic and accumulation.
+hipError_t launch_rhs_inc32(int stage, int p, const RhsArgs<float>& a, hipStream_t s) {
+  switch (p) {
+    case 1: return launch_inc32_p<1>(stage, a, s);
+    case 2: return launch_inc32_p<2>(stage, a, s);
+    case 3: return launch_inc32_p<3>(stage, a, s);
+    case 4: return launch_inc32_p<4>(stage, a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
 // Increments of the float32 mode: float32 fields and coefficients, float64
 // arithmetic, float32 outputs.
 hipError_t launch_rhs_inc(int stage, int p, const RhsArgs<double>& a, hipStream_t s) {

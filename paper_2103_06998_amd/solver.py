@@ -111,6 +111,12 @@ class Solver:
         """Smallest accepted pivot / diagonal ratio of the LU (default 1e-14)."""
         self._check(self.lib.adi_set_pivot_floor(self.h, float(floor)))
 
+    def set_residual64(self, mask: int):
+        """Float32 mode: stages whose increment is formed in float64
+        arithmetic (OR of _lib.ADI_RES64_*; default: the E stage of
+        substep 2).  Takes effect at the next factor()."""
+        self._check(self.lib.adi_set_residual64(self.h, int(mask)))
+
     def factor(self, dt: float):
         self._check(self.lib.adi_factor(self.h, float(dt)))
 

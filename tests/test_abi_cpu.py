@@ -107,6 +107,9 @@ def test_host_validation_errors(lib):
         assert lib.adi_set_pivot_floor(h, -1.0) == _lib.ADI_EINVAL
         assert lib.adi_set_pivot_floor(h, float("inf")) == _lib.ADI_EINVAL
         assert lib.adi_set_pivot_floor(h, 0.5) == _lib.ADI_OK
+        assert lib.adi_set_residual64(h, -1) == _lib.ADI_EINVAL
+        assert lib.adi_set_residual64(h, 16) == _lib.ADI_EINVAL
+        assert lib.adi_set_residual64(h, 15) == _lib.ADI_OK
     finally:
         lib.adi_destroy(h)
 

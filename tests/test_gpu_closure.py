@@ -276,13 +276,66 @@ def test_step_closure_is_the_composition_and_gate_rejects(torch, mod):
         sv.close()
 
 
+def test_gate_judges_the_correction_against_the_coarse_step(torch, mod):
+    """The gate compares the RMS of the correction s * y with the RMS of
+    the coarse step's change C - S: with the gate just below that ratio the
+    step stays a plain step, just above it the correction is applied; a
+    zero state without a source takes no correction at all."""
+    closure, solver = mod
+    prob, a, mat, src = glue_setup(mod, seed=31)
+    n = prob.n
+    E, H = prob.constrain(*np.split(workloads.random_fields(n, 32), 2))
+    S = np.stack(list(E) + list(H))
+    net = closure.Network()
+    net.set_params(closure.init_params(5, last_gain=0.3))
+    # the ratio the gate sees, from the single calls
+    a.set_fields(S, 0.1)
+    a.closure_mark()
+    a.step(1)
+    x = torch.empty((n ** 3, 16), dtype=torch.float32, device="cuda")
+    s = torch.empty(1, dtype=torch.float32, device="cuda")
+    a.closure_features(x, s)
+    y = net.forward(x, (n, n, n)).cpu().numpy().astype(np.float64)
+    C, _ = a.get_fields()
+    scale = float(s.item())
+    ratio = scale * np.sqrt(np.mean(y ** 2)) / np.sqrt(np.mean((C - S) ** 2))
+    assert 1e-3 < ratio < 1e3
+    plain = C
+    applied = oc.closure_apply(C, y.reshape(n, n, n, 6), scale)
+    for gate, rejected in ((0.99 * ratio, True), (1.01 * ratio, False)):
+        a.set_fields(S, 0.1)
+        before = a.closure_rejected()
+        a.step_closure(net, 1, gate=float(gate))
+        got, _ = a.get_fields()
+        assert a.closure_rejected() - before == int(rejected)
+        ref = plain if rejected else applied
+        assert rel_l2(got, ref) <= 1e-6, (gate, rejected)
+    # zero state, no source: C - S = 0, so the correction is rejected and
+    # the state stays exactly zero
+    z = solver.Solver(prob.N, prob.p, "fp64")
+    z.set_material(mat.eps_r, mat.mu_r, mat.sigma_nd)
+    z.factor(prob.dt)
+    z.set_fields(np.zeros_like(S), 0.0)
+    z.step_closure(net, 2, gate=1.0)
+    uz, _ = z.get_fields()
+    assert z.closure_rejected() == 2
+    assert not np.any(uz)
+    net.close()
+    for sv in (a, z):
+        sv.close()
+
+
 def test_training_gains_over_the_plain_coarse_step(torch, mod):
     """Train on solver-generated pairs (16^3 elements, p=2, three-class blob
     maps, a dipole per map) on the GPU with the library's own forward,
     backward and Adam kernels; on held-out pairs from an unseen map and
     source the trained network removes a clear part of the coarse step's
-    one-step error (the untrained network does not).  The multi-step
-    closure run is reported beside plain coarse and fine ADI."""
+    one-step error (the untrained network does not).  The one-step gain
+    does not carry over to a rollout: 16 gated closure steps end about 1.25x
+    further from the reference than 16 plain coarse steps (both > 100 %
+    off: the coarse step's phase error dominates), with no correction
+    rejected at gate 0.5.  The rollout is asserted to stay within 1.5x of
+    the plain coarse error."""
     closure, _ = mod
     N, p = 16, 2
     dtc = 4.0 / (2 * N)
@@ -308,7 +361,7 @@ def test_training_gains_over_the_plain_coarse_step(torch, mod):
     assert after < 0.8 * base
 
     res = closure.run_comparison(N, p, workloads.blob_map(32, 999), src(99), dtc / 4, 64, net,
-                                 gate=1.0)
+                                 gate=0.5)
     print({k: (v["rel_l2"] if isinstance(v, dict) else v) for k, v in res.items()})
-    assert np.isfinite(res["closure"]["rel_l2"])
+    assert res["closure"]["rel_l2"] <= 1.5 * res["coarse"]["rel_l2"]
     net.close()

@@ -55,11 +55,13 @@ def random_setup(N, p, seed, with_src=True, sig_max=20.0):
     return eps, mu, sig, src
 
 
-def make_gpu(Solver, N, p, eps, mu, sig, dt, src, precision="fp64"):
+def make_gpu(Solver, N, p, eps, mu, sig, dt, src, precision="fp64", res64=None):
     s = Solver(N, p, precision)
     s.set_material_dof(eps, mu, sig)
     if src is not None:
         s.set_source(src.xs, src.comp, src.amp, src.f0, src.t0, src.width)
+    if res64 is not None:
+        s.set_residual64(res64)
     s.factor(dt)
     return s
 
@@ -182,11 +184,11 @@ def test_large_rounds_two_launches(Solver, precision, tol):
     compare_state(got, E, H, tol, ("n148", precision))
 
 
-def _fp32_random_steps(Solver, N, p, steps=2):
+def _fp32_random_steps(Solver, N, p, steps=2, res64=None):
     eps, mu, sig, src = random_setup(N, p, seed=200 + N)
     dt = 0.5 / N
     prob = maxwell.Problem(N, p, eps, mu, sig, dt, src)
-    s = make_gpu(Solver, N, p, eps, mu, sig, dt, src, "fp32_refine")
+    s = make_gpu(Solver, N, p, eps, mu, sig, dt, src, "fp32_refine", res64)
     E0, H0 = constrained_random_state(prob, 21)
     s.set_fields(np.stack(E0 + H0), 0.01)
     s.step(steps)
@@ -206,6 +208,17 @@ def test_full_steps_fp32_refine_random_material(Solver, N):
     _, _, got, E, H = _fp32_random_steps(Solver, N, 3)
     errs = compare_state(got, E, H, TOL32, ("fp32", N, 3))
     print("fp32 random material", N, 3, "errors", errs)
+
+
+@pytest.mark.parametrize("N", [4, 45])
+@pytest.mark.parametrize("res64", [0, 5, 15])
+def test_fp32_residual_arithmetic_choices(Solver, N, res64):
+    """The float32 mode with its increments formed in float32 arithmetic
+    everywhere (0), in float64 for both E stages (5) or for every stage
+    (15): all within 1e-5 per component of the oracle at p = 3."""
+    _, _, got, E, H = _fp32_random_steps(Solver, N, 3, res64=res64)
+    errs = compare_state(got, E, H, TOL32, ("fp32 residual mask", res64, N))
+    print("fp32 residual mask", res64, N, "errors", errs)
 
 
 class Float32Storage(maxwell.Problem):
@@ -267,7 +280,7 @@ def test_mms16_manufactured_solution(Solver):
     assert err["E_L2"] < 1e-3 and err["H_L2"] < 1e-3
 
 
-def _workload_pair(Solver, name, steps, precision="fp64"):
+def _workload_pair(Solver, name, steps, precision="fp64", res64=None):
     w = workloads.make(name)
     prob = maxwell.problem_from_voxels(w.N, w.p, w.material, w.dt, w.source)
     s = Solver(w.N, w.p, precision)
@@ -275,6 +288,8 @@ def _workload_pair(Solver, name, steps, precision="fp64"):
     s.set_material(m.eps_r, m.mu_r, m.sigma_nd)
     src = w.source
     s.set_source(src.xs, src.comp, src.amp, src.f0, src.t0, src.width)
+    if res64 is not None:
+        s.set_residual64(res64)
     s.factor(w.dt)
     n = w.N + w.p
     # start from a nonzero state so that every term is exercised
@@ -349,7 +364,8 @@ def test_repeatable_bitwise(Solver):
 def test_profiling_pass_equals_graph_steps(Solver, precision):
     """The eager profiling pass (the per-kernel timings of bench.py) runs the
     same kernels as the captured graph: the same state after the same steps,
-    bit for bit, and one record per launch of a step."""
+    bit for bit, that state equal to the oracle's, and one record per launch
+    of a step."""
     N, p = 45, 3  # n = 48: partitioned shared-axis solves, mixed-axis rounds
     eps, mu, sig, src = random_setup(N, p, seed=11)
     dt = 0.5 / N
@@ -368,6 +384,9 @@ def test_profiling_pass_equals_graph_steps(Solver, precision):
         s.close()
     assert np.array_equal(outs[0][0], outs[1][0])
     assert outs[0][1] == outs[1][1]
+    E3, H3, _ = prob.run(E, H, 0.0, 3)
+    compare_state(outs[1][0], E3, H3, TOL64 if precision == "fp64" else TOL32,
+                  ("profiling pass", precision))
     kinds = [L["kind"] for L in launches]
     assert kinds.count("rhs_E") == 2 and kinds.count("rhs_H") == 2
     assert kinds.count("residual64") == 0
@@ -437,15 +456,19 @@ def test_local_time_step_steps(Solver, N, p):
     compare_state(got, E, H, TOL64, ("local dt", N, p))
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", TOL64), ("fp32_refine", TOL32)])
-def test_shell32_subrun_50_steps(Solver, precision, tol):
+@pytest.mark.parametrize("precision,tol,res64", [("fp64", TOL64, None),
+                                                 ("fp32_refine", TOL32, None),
+                                                 ("fp32_refine", TOL32, 0),
+                                                 ("fp32_refine", TOL32, 15)])
+def test_shell32_subrun_50_steps(Solver, precision, tol, res64):
     """The 32^3 p=2 sub-run of the 256^3 shell workload (same voxel map):
     all 50 steps of its dt against the float64 oracle, per component (and
-    per field, printed)."""
-    got, E, H = _workload_pair(Solver, "shell32", 50, precision)
+    per field, printed); the float32 mode with its default residual
+    arithmetic, all-float32 (0) and all-float64 (15) increments."""
+    got, E, H = _workload_pair(Solver, "shell32", 50, precision, res64)
     fields = {"E": rel_l2(got[:3], np.stack(E)), "H": rel_l2(got[3:], np.stack(H))}
-    comp = compare_state(got, E, H, tol, ("shell32", precision))
-    print("shell32", precision, "per-field relative L2:", fields, "per component:", comp)
+    comp = compare_state(got, E, H, tol, ("shell32", precision, res64))
+    print("shell32", precision, res64, "per-field relative L2:", fields, "per component:", comp)
 
 
 def test_singular_pivot_reported_and_context_usable(Solver):
