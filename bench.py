@@ -87,14 +87,15 @@ def kernel_key(launch, nth, n, p, precision, res64=RES64_DEFAULT):
         TC = "double" if res64 & bit else "float"
         return f"rhs_kernel<float, {TC}, float, float, {p}, {stage}>"
     spike = 48 <= n <= 288 and launch["nmod"] == 0
-    m = (n + 3) // 4  # rows per segment of the partitioned solve
-    MR = next(r for r in (24, 36, 48, 72) if m <= r)
+    S = 8 if n >= 193 else 4  # segments per line of the partitioned solve
+    m = (n + S - 1) // S      # rows per segment
+    MR = next(r for r in (24, 36, 48) if m <= r)
     mod = "true" if launch["nmod"] else "false"
     if k == "sweep_xyz":
-        return f"spike_mixed_kernel<{T}, {p}, {MR}>" if spike else \
+        return f"spike_mixed_kernel<{T}, {p}, {MR}, {S}>" if spike else \
             f"sweep_mixed_kernel<{T}, {p}, {mod}>"
     xax = "true" if k == "sweep_x" else "false"
-    return f"spike_kernel<{T}, {p}, {xax}, {MR}>" if spike else \
+    return f"spike_kernel<{T}, {p}, {xax}, {MR}, {S}>" if spike else \
         f"sweep_kernel<{T}, {p}, {xax}, {mod}>"
 
 

@@ -165,7 +165,7 @@ size_t layout(adi_ctx* c, unsigned char* base) {
     c->bandT[ax] = take(size_t(4) * n * W * es);
     c->band64[ax] = reinterpret_cast<double*>(take(size_t(4) * n * W * 8));
     c->fb64[ax] = reinterpret_cast<double*>(take(size_t(2) * n * W * 8));
-    const int q = 2 * P * (kSpikeS - 1);
+    const int q = 2 * P * (spike_segments(n) - 1);
     for (int v = 0; v < 2; ++v) {
       c->shL[ax][v] = take(size_t(n) * P * es);
       c->shU[ax][v] = take(size_t(n) * P * es);
@@ -313,17 +313,19 @@ SweepDesc desc_for(adi_ctx* c, int kindH, int sub, int comp_i, int axis, void* i
     d.U = c->shU[axis][v];
     d.D = c->shD[axis][v];
     d.spk = c->spike_ok[axis] ? c->spk[axis][v] : nullptr;
+    d.segs = spike_segments(c->ns[axis]);
     d.modified = 0;
   }
   return d;
 }
 
 // Partitioned solves for a launch: every descriptor shared, with
-// partition data for its axis.
+// partition data for its axis, all with the same segment count (returned;
+// 0 = one lane per line).
 int spike_for(const SweepArgs& a, int nd) {
   for (int q = 0; q < nd; ++q)
-    if (a.d[q].modified || !a.d[q].spk) return 0;
-  return nd > 0 ? 1 : 0;
+    if (a.d[q].modified || !a.d[q].spk || a.d[q].segs != a.d[0].segs) return 0;
+  return nd > 0 ? a.d[0].segs : 0;
 }
 
 // Blocks of 64 lines a launch of these descriptors runs per descriptor.
@@ -870,7 +872,7 @@ int adi_factor(adi_ctx* c, double dt) {
         std::vector<double> band = g.M;
         if (v) apply_dirichlet(band, n, p);
         SpikeData sd;
-        ok = spike_prepare(band, n, p, kSpikeS, sd);
+        ok = spike_prepare(band, n, p, spike_segments(n), sd);
         if (!ok) break;
         for (const std::vector<double>* part : {&sd.L, &sd.DU, &sd.D, &sd.V, &sd.W, &sd.R})
           pack[v].insert(pack[v].end(), part->begin(), part->end());
@@ -1473,6 +1475,7 @@ hipError_t enqueue_mass_solves(adi_ctx* c, int kindH, void* buf, hipStream_t s) 
       d.U = c->shU[ax][v];
       d.D = c->shD[ax][v];
       d.spk = c->spike_ok[ax] ? c->spk[ax][v] : nullptr;
+      d.segs = spike_segments(c->ns[ax]);
       d.modified = 0;
     }
     for (int k = 0; k < 3; ++k) w.dim[k] = c->ns[k];

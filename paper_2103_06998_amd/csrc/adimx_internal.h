@@ -11,7 +11,11 @@
 namespace adimx {
 
 constexpr int kMaxP = 4;    // largest supported B-spline degree
-constexpr int kSpikeS = 4;  // segments per line of the partitioned line solve
+// Segments per line of the partitioned line solve: 4, or 8 for lines of
+// more than kSpikeS8MinN rows (segments of at most 36 rows either way in the
+// benchmarked sizes; shorter segments need fewer registers per wave).
+constexpr int kSpikeS = 4, kSpikeS8 = 8, kSpikeS8MinN = 193;
+constexpr int spike_segments(int n) { return n >= kSpikeS8MinN ? kSpikeS8 : kSpikeS; }
 // Lines of n rows use the partitioned solve when kSpikeMinN <= n <= kSpikeMaxN.
 constexpr int kSpikeMinN = 48, kSpikeMaxN = 288;
 
@@ -101,6 +105,7 @@ struct SweepDesc {
   const void* D;          // inverse diagonal; shared: [r], modified: [(l/64 * n + r) * 64 + l%64]
   const void* spk;        // shared factors only: partitioned-solve data (L, DU, D, V, W
                           // as [r*P + k] / [r], then R, q x q), or null
+  int segs;               // segments per line of spk (spike_segments(n))
   int modified;           // 0 = shared factors, 1 = per-line factors
 };
 
@@ -111,7 +116,8 @@ struct SweepArgs {
                           // nx ny nz / dim[axis] of them
   int xaxis;              // 0: y/z lines, 1: x lines (transposing kernel),
                           // 2: both, descriptors of x lines first
-  int spike;              // 1: shared-factor lines solved in kSpikeS segments each
+  int spike;              // 0, or the segments per line (every descriptor's segs) of
+                          // the partitioned solve of shared-factor lines
   double* tick_t;         // if non-null, block (0,0) thread 0 does *tick_t += tick_dt
   double tick_dt;
 };

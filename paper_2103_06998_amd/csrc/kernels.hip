@@ -847,11 +847,11 @@ __device__ __forceinline__ void sweep_body(const SweepArgs& a) {
 }
 
 // ------------------------------------------------------------ partitioned sweep
-// Shared-factor lines, each split into kSpikeS row segments solved by the
-// kSpikeS waves of a block (wave = segment, lane = line, 64 lines per
-// block); a segment's rows stay in registers.  Per line:
+// Shared-factor lines, each split into S row segments (4, or 8 for long
+// lines) solved by the S waves of a block (wave = segment, lane = line, 64
+// lines per block); a segment's rows stay in registers.  Per line:
 //   1. g = A_s^{-1} b on every segment (block-diagonal LU, forward and
-//      backward recurrences of m = n / kSpikeS rows instead of n);
+//      backward recurrences of m = n / S rows instead of n);
 //   2. the p values at both ends of every segment go through LDS, and each
 //      segment forms the 2p interface unknowns it needs from the
 //      precomputed inverse R of the reduced system: T (top p rows of the
@@ -859,9 +859,9 @@ __device__ __forceinline__ void sweep_body(const SweepArgs& a) {
 //   3. x = g - V T - W U with the precomputed spikes V, W.
 // The factors, spikes and R of the descriptor are staged in LDS (broadcast
 // reads: every lane of a wave reads the same row).
-template <typename T, int P, bool XAX, int MR>
+template <typename T, int P, bool XAX, int MR, int S>
 __device__ __forceinline__ void spike_body(const SweepArgs& a) {
-  constexpr int S = kSpikeS, Q = 2 * P * (S - 1);
+  constexpr int Q = 2 * P * (S - 1);
   extern __shared__ __align__(16) unsigned char smem[];
   T* sf = reinterpret_cast<T*>(smem);
   const SweepDesc& ds = a.d[blockIdx.y];
@@ -1112,14 +1112,14 @@ __global__ __launch_bounds__(64) void sweep_mixed_kernel(SweepArgs a) {
   if (a.d[blockIdx.y].axis == 0) sweep_body<T, P, true, MOD>(a);
   else sweep_body<T, P, false, MOD>(a);
 }
-template <typename T, int P, bool XAX, int MR>
-__global__ __launch_bounds__(64 * kSpikeS) void spike_kernel(SweepArgs a) {
-  spike_body<T, P, XAX, MR>(a);
+template <typename T, int P, bool XAX, int MR, int S>
+__global__ __launch_bounds__(64 * S) void spike_kernel(SweepArgs a) {
+  spike_body<T, P, XAX, MR, S>(a);
 }
-template <typename T, int P, int MR>
-__global__ __launch_bounds__(64 * kSpikeS) void spike_mixed_kernel(SweepArgs a) {
-  if (a.d[blockIdx.y].axis == 0) spike_body<T, P, true, MR>(a);
-  else spike_body<T, P, false, MR>(a);
+template <typename T, int P, int MR, int S>
+__global__ __launch_bounds__(64 * S) void spike_mixed_kernel(SweepArgs a) {
+  if (a.d[blockIdx.y].axis == 0) spike_body<T, P, true, MR, S>(a);
+  else spike_body<T, P, false, MR, S>(a);
 }
 
 // ------------------------------------------------------------ factorisation
@@ -1294,59 +1294,57 @@ hipError_t launch_sweep_mixed(int ndesc, const SweepArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <typename T, int P, bool XAX, int MR>
+template <typename T, int P, bool XAX, int MR, int S>
 hipError_t launch_spike_k(int ndesc, const SweepArgs& a, hipStream_t s) {
-  constexpr int Q = 2 * P * (kSpikeS - 1);
+  constexpr int Q = 2 * P * (S - 1);
   const LaunchShape sh = launch_shape(ndesc, a);
   const size_t lds = (size_t(sh.nmax) * (4 * P + 1) + Q * Q + size_t(Q) * 64 +
-                      (XAX ? size_t(kSpikeS) * 8 * 65 : 0)) * sizeof(T);
+                      (XAX ? size_t(S) * 8 * 65 : 0)) * sizeof(T);
   dim3 grid((sh.lines + 63) / 64, ndesc);
-  auto k = spike_kernel<T, P, XAX, MR>;
+  auto k = spike_kernel<T, P, XAX, MR, S>;
   hipError_t e = set_lds(k, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k, grid, dim3(64 * kSpikeS), lds, s, a);
+  hipLaunchKernelGGL(k, grid, dim3(64 * S), lds, s, a);
   return hipGetLastError();
 }
 
-template <typename T, int P, int MR>
+template <typename T, int P, int MR, int S>
 hipError_t launch_spike_mixed_k(int ndesc, const SweepArgs& a, hipStream_t s) {
-  constexpr int Q = 2 * P * (kSpikeS - 1);
+  constexpr int Q = 2 * P * (S - 1);
   const LaunchShape sh = launch_shape(ndesc, a);
   const size_t lds = (size_t(sh.nmax) * (4 * P + 1) + Q * Q + size_t(Q) * 64 +
-                      size_t(kSpikeS) * 8 * 65) * sizeof(T);
+                      size_t(S) * 8 * 65) * sizeof(T);
   dim3 grid((sh.lines + 63) / 64, ndesc);
-  auto k = spike_mixed_kernel<T, P, MR>;
+  auto k = spike_mixed_kernel<T, P, MR, S>;
   hipError_t e = set_lds(k, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k, grid, dim3(64 * kSpikeS), lds, s, a);
+  hipLaunchKernelGGL(k, grid, dim3(64 * S), lds, s, a);
   return hipGetLastError();
 }
+
+template <typename T, int P, int MR, int S>
+hipError_t launch_spike_xs(int xaxis, int ndesc, const SweepArgs& a, hipStream_t s) {
+  if (xaxis == 2) return launch_spike_mixed_k<T, P, MR, S>(ndesc, a, s);
+  return xaxis ? launch_spike_k<T, P, true, MR, S>(ndesc, a, s)
+               : launch_spike_k<T, P, false, MR, S>(ndesc, a, s);
+}
+
 // xaxis: 0 = y/z lines, 1 = x lines, 2 = both (descriptor axis per block)
 template <typename T, int P>
 hipError_t launch_spike_x(int xaxis, int ndesc, const SweepArgs& a, hipStream_t s) {
-  // register rows per segment: ceil(n / kSpikeS) of the longest line,
-  // rounded up to the nearest instantiated length (padding rows cost work)
-  const int m = (launch_shape(ndesc, a).nmax + kSpikeS - 1) / kSpikeS;
-  if (m <= 24) {
-    if (xaxis == 2) return launch_spike_mixed_k<T, P, 24>(ndesc, a, s);
-    return xaxis ? launch_spike_k<T, P, true, 24>(ndesc, a, s)
-                 : launch_spike_k<T, P, false, 24>(ndesc, a, s);
+  // register rows per segment: ceil(n / S) of the longest line, rounded up
+  // to the nearest instantiated length (padding rows cost work); lines of
+  // n >= kSpikeS8MinN (<= kSpikeMaxN) have 8 segments of at most 36 rows
+  const int nmax = launch_shape(ndesc, a).nmax;
+  if (a.spike == kSpikeS8) {
+    if ((nmax + kSpikeS8 - 1) / kSpikeS8 > 36) return hipErrorInvalidValue;
+    return launch_spike_xs<T, P, 36, kSpikeS8>(xaxis, ndesc, a, s);
   }
-  if (m <= 36) {
-    if (xaxis == 2) return launch_spike_mixed_k<T, P, 36>(ndesc, a, s);
-    return xaxis ? launch_spike_k<T, P, true, 36>(ndesc, a, s)
-                 : launch_spike_k<T, P, false, 36>(ndesc, a, s);
-  }
-  if (m <= 48) {
-    if (xaxis == 2) return launch_spike_mixed_k<T, P, 48>(ndesc, a, s);
-    return xaxis ? launch_spike_k<T, P, true, 48>(ndesc, a, s)
-                 : launch_spike_k<T, P, false, 48>(ndesc, a, s);
-  }
-  if (m <= 72) {
-    if (xaxis == 2) return launch_spike_mixed_k<T, P, 72>(ndesc, a, s);
-    return xaxis ? launch_spike_k<T, P, true, 72>(ndesc, a, s)
-                 : launch_spike_k<T, P, false, 72>(ndesc, a, s);
-  }
+  if (a.spike != kSpikeS) return hipErrorInvalidValue;
+  const int m = (nmax + kSpikeS - 1) / kSpikeS;
+  if (m <= 24) return launch_spike_xs<T, P, 24, kSpikeS>(xaxis, ndesc, a, s);
+  if (m <= 36) return launch_spike_xs<T, P, 36, kSpikeS>(xaxis, ndesc, a, s);
+  if (m <= 48) return launch_spike_xs<T, P, 48, kSpikeS>(xaxis, ndesc, a, s);
   return hipErrorInvalidValue;
 }
 
@@ -1359,7 +1357,9 @@ hipError_t launch_sweep_p(int ndesc, const SweepArgs& a, hipStream_t s) {
   if (a.spike && !mod) {
     for (int i = 0; i < ndesc; ++i) {
       const int n = a.dim[a.d[i].axis];
-      if (!a.d[i].spk || n < kSpikeMinN || n > kSpikeMaxN) return hipErrorInvalidValue;
+      if (!a.d[i].spk || a.d[i].segs != a.spike || spike_segments(n) != a.spike ||
+          n < kSpikeMinN || n > kSpikeMaxN)
+        return hipErrorInvalidValue;
     }
     return launch_spike_x<T, P>(a.xaxis, ndesc, a, s);
   }

@@ -118,7 +118,9 @@ def test_rhs_stage(Solver, N, p, stage, sub):
 
 # n = N + p >= 48 takes the partitioned (4 segments per line) solve for the
 # shared-factor axes: n = 48, 54, 59 and 72 cover even and ragged segments
-# and every degree; (160, 2) takes the longer register segments (n = 162).
+# and every degree; (160, 2) takes the longer register segments (n = 162);
+# n >= 193 takes 8 segments per line: (196, 3) ragged (n = 199), (256, 2)
+# the lines of the 256^3 workload (n = 258).
 @pytest.mark.parametrize("N,p", [(1, 2), (3, 1), (5, 2), (4, 3), (9, 3), (33, 2), (45, 3),
                                  (50, 4), (58, 1), (70, 2)])
 @pytest.mark.parametrize("stage,sub", [(0, 1), (0, 2), (1, 1), (1, 2)])
@@ -126,9 +128,10 @@ def test_solve_stage(Solver, N, p, stage, sub):
     _solve_stage(Solver, N, p, stage, sub)
 
 
+@pytest.mark.parametrize("N,p", [(160, 2), (196, 3), (256, 2)])
 @pytest.mark.parametrize("stage,sub", [(0, 2), (1, 1)])
-def test_solve_stage_long_lines(Solver, stage, sub):
-    _solve_stage(Solver, 160, 2, stage, sub)
+def test_solve_stage_long_lines(Solver, N, p, stage, sub):
+    _solve_stage(Solver, N, p, stage, sub)
 
 
 def _solve_stage(Solver, N, p, stage, sub):
@@ -164,13 +167,15 @@ def test_full_steps_random_material(Solver, N, p, steps):
     compare_state(got, E, H, TOL64, (N, p))
 
 
+@pytest.mark.parametrize("N", [146, 196])
 @pytest.mark.parametrize("precision,tol", [("fp64", TOL64), ("fp32_refine", TOL32)])
-def test_large_rounds_two_launches(Solver, precision, tol):
+def test_large_rounds_two_launches(Solver, precision, tol, N):
     """n = 148: a solve round's x and y/z lines (3 x 343 blocks of 64 lines)
     exceed the single-launch limit of 1024 blocks, so each round runs as two
     concurrent launches joined by events (smaller grids take one mixed-axis
-    launch); one step against the oracle."""
-    N, p = 146, 2
+    launch); n = 198 also takes the 8-segment partitioned solve.  One step
+    against the oracle."""
+    p = 2
     eps, mu, sig, src = random_setup(N, p, seed=7)
     dt = 0.5 / N
     prob = maxwell.Problem(N, p, eps, mu, sig, dt, src)
@@ -181,7 +186,7 @@ def test_large_rounds_two_launches(Solver, precision, tol):
     s.step(1)
     E, H, t = prob.run(E, H, t, 1)
     got, _ = s.get_fields()
-    compare_state(got, E, H, tol, ("n148", precision))
+    compare_state(got, E, H, tol, ("n", N + p, precision))
 
 
 def _fp32_random_steps(Solver, N, p, steps=2, res64=None):
