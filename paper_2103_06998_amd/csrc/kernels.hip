@@ -174,11 +174,22 @@ size_t rhs_lds_bytes(int zchunk) {
 // pending plane is complete it is scaled by the per-row coefficients and
 // written.  TI: input type, TC: arithmetic type, TO: output type, TK:
 // coefficient type.
-template <typename TI, typename TC, typename TO, typename TK, int P, int STAGE>
-__global__ __launch_bounds__(kRhsThreads) void rhs_kernel(RhsArgs<TC> a,
-                                                          const TC* __restrict__ bandx,
-                                                          const TC* __restrict__ bandy,
-                                                          const TC* __restrict__ zw) {
+// One block's work: the tile (bx, by), z chunk bz of output component
+// COMP, or of comp_rt when COMP < 0.  With a compile-time component its
+// terms, field slots and boundary rule are fixed in the code and no term is
+// skipped by a branch, which lets the compiler batch the LDS reads of all
+// its terms: float32 arithmetic takes that form (E right-hand side 136 ->
+// 126 us at 128^3 p=3), and so does float64 arithmetic up to p = 2 (the
+// 256^3 p=2 step: 4.22 -> 4.13 ms in the float32 mode).  In float64
+// arithmetic at p >= 3 the batched reads need more registers than there are
+// and the kernel slows down (128^3 p=3: 150 -> 218 us), so it keeps the
+// runtime component.
+template <typename TI, typename TC, typename TO, typename TK, int P, int STAGE, int COMP>
+__device__ __forceinline__ void rhs_tile(const RhsArgs<TC>& a, const TC* __restrict__ bandx,
+                                         const TC* __restrict__ bandy,
+                                         const TC* __restrict__ zw, int bx, int by, int bz,
+                                         int comp_rt) {
+  const int comp = COMP >= 0 ? COMP : comp_rt;
   constexpr int W = 2 * P + 1, HX = kTX + 2 * P, HY = kTY + 2 * P;
   constexpr int NT = StageInfo<STAGE>::NT, NG = StageInfo<STAGE>::NG;
   constexpr CompTab CT = make_comp_tab<STAGE>();
@@ -199,26 +210,6 @@ __global__ __launch_bounds__(kRhsThreads) void rhs_kernel(RhsArgs<TC> a,
   const size_t plane = size_t(nx) * ny;
   const int tid = threadIdx.x;
   const int wave = tid / 64, lane = tid % 64;
-  // Work item of this block.  Workgroups are dealt to the 8 XCDs (each with
-  // its own L2) round robin by linear id; item w = ((zc * nty + ty) * ntx +
-  // tx) * 3 + component is assigned so that each XCD runs a contiguous range
-  // of items: the three components of a tile and its x neighbours share
-  // their inputs in one L2.
-  int comp, bx, by, bz;
-  {
-    const int ntx = gridDim.x / 3, nty = gridDim.y;
-    const int total = gridDim.x * gridDim.y * gridDim.z;
-    const int b = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
-    const int xcd = b % kXcds, k = b / kXcds;
-    const int q = total / kXcds, r = total % kXcds;
-    int w = xcd * q + min(xcd, r) + k;
-    comp = w % 3;
-    w /= 3;
-    bx = w % ntx;
-    w /= ntx;
-    by = w % nty;
-    bz = w / nty;
-  }
   const int tx = tid % kTX, ty = tid / kTX;
   const int i0 = bx * kTX, j0 = by * kTY;
   const int t0 = bz * a.zchunk;
@@ -408,6 +399,40 @@ __global__ __launch_bounds__(kRhsThreads) void rhs_kernel(RhsArgs<TC> a,
       emit(te, c);
     }
     shift();
+  }
+}
+
+template <typename TI, typename TC, typename TO, typename TK, int P, int STAGE>
+__global__ __launch_bounds__(kRhsThreads) void rhs_kernel(RhsArgs<TC> a,
+                                                          const TC* __restrict__ bandx,
+                                                          const TC* __restrict__ bandy,
+                                                          const TC* __restrict__ zw) {
+  // Work item of this block.  Workgroups are dealt to the 8 XCDs (each with
+  // its own L2) round robin by linear id; item w = ((zc * nty + ty) * ntx +
+  // tx) * 3 + component is assigned so that each XCD runs a contiguous range
+  // of items: the three components of a tile and its x neighbours share
+  // their inputs in one L2.
+  int comp, bx, by, bz;
+  {
+    const int ntx = gridDim.x / 3, nty = gridDim.y;
+    const int total = gridDim.x * gridDim.y * gridDim.z;
+    const int b = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+    const int xcd = b % kXcds, k = b / kXcds;
+    const int q = total / kXcds, r = total % kXcds;
+    int w = xcd * q + min(xcd, r) + k;
+    comp = w % 3;
+    w /= 3;
+    bx = w % ntx;
+    w /= ntx;
+    by = w % nty;
+    bz = w / nty;
+  }
+  if constexpr (sizeof(TC) == 4 || P <= 2) {
+    if (comp == 0) rhs_tile<TI, TC, TO, TK, P, STAGE, 0>(a, bandx, bandy, zw, bx, by, bz, 0);
+    else if (comp == 1) rhs_tile<TI, TC, TO, TK, P, STAGE, 1>(a, bandx, bandy, zw, bx, by, bz, 1);
+    else rhs_tile<TI, TC, TO, TK, P, STAGE, 2>(a, bandx, bandy, zw, bx, by, bz, 2);
+  } else {
+    rhs_tile<TI, TC, TO, TK, P, STAGE, -1>(a, bandx, bandy, zw, bx, by, bz, comp);
   }
 }
 
