@@ -38,6 +38,9 @@ def main(argv=None):
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--gate", type=float, default=0.5)
     ap.add_argument("--eval", choices=("shell128", "blob"), default="shell128")
+    ap.add_argument("--dagger", type=int, default=0,
+                    help="rounds of extra pairs sampled along the closure's own "
+                         "trajectories, each followed by more training")
     ap.add_argument("--eval-seeds", type=int, nargs="*", default=[9001, 9002, 9003])
     ap.add_argument("--save", default="")
     args = ap.parse_args(argv)
@@ -74,6 +77,17 @@ def main(argv=None):
     t0 = time.time()
     closure.train(net, pairs, iters=args.iters, lr=args.lr, lr_final=1e-5,
                   log_every=max(1, args.iters // 8), log=log)
+    for r in range(args.dagger):
+        # states the closure itself visits (its own trajectory, gated), on
+        # the first 16 training maps, then more training on all pairs
+        chunk = seeds[:16]
+        pairs = closure.generate_pairs(N, p, [workloads.blob_map(N, s) for s in chunk],
+                                       [train_source(s) for s in chunk], dtc, 4,
+                                       pairs_per_map=args.pairs_per_map // 2, every=2,
+                                       warmup=4, pairs=pairs, rollout_net=net, gate=args.gate)
+        closure.train(net, pairs, iters=args.iters // 2, lr=args.lr / 4, lr_final=1e-5,
+                      seed=r + 1, log_every=max(1, args.iters // 4), log=log)
+        log(f"dagger round {r + 1}: {len(pairs.x)} pairs")
     torch.cuda.synchronize()
     train_s = time.time() - t0
     held_ratio = closure.evaluate_loss(net, held) / closure.target_energy(held)
@@ -97,7 +111,7 @@ def main(argv=None):
                    rejected=res.get("rejected", 0), speedup_vs_fine=res["speedup_vs_fine"])
         rows.append(row)
         log(json.dumps(row))
-    summary = dict(eval=args.eval, train_p=p, train_N=N, pairs=len(pairs.x), iters=args.iters,
+    summary = dict(eval=args.eval, dagger=args.dagger, train_p=p, train_N=N, pairs=len(pairs.x), iters=args.iters,
                    train_s=round(train_s, 2), pair_gen_s=round(gen_s, 2),
                    held_one_step_ratio=round(held_ratio, 4), gate=args.gate,
                    mean_fine_err=float(np.mean([r["fine_err"] for r in rows])),

@@ -333,6 +333,57 @@ def test_shell128_p3_full_size_fp64(Solver):
     compare_state(got, E, H, TOL64, "shell128")
 
 
+def _run_gpu_workload(Solver, name, precision, checkpoints):
+    """States of a workload's run from a zero state at the given step counts."""
+    w = workloads.make(name)
+    s = Solver(w.N, w.p, precision)
+    m = w.material
+    s.set_material(m.eps_r, m.mu_r, m.sigma_nd)
+    src = w.source
+    s.set_source(src.xs, src.comp, src.amp, src.f0, src.t0, src.width)
+    s.factor(w.dt)
+    n = w.N + w.p
+    s.set_fields(np.zeros((6, n, n, n)), 0.0)
+    out, done = [], 0
+    for k in checkpoints:
+        s.step(k - done)
+        done = k
+        out.append(s.get_fields())
+    s.close()
+    return out
+
+
+@pytest.mark.parametrize("name,steps", [("blob64", 100), ("shell128", 200)])
+def test_configured_lengths_fp32_against_fp64(Solver, name, steps):
+    """The 64^3 and 128^3 workloads over their configured lengths (100 and
+    200 steps from a zero state, the dipole driving the fields): the float32
+    mode against the float64 path (itself equal to the oracle to 1e-12 per
+    step at these sizes).  Bound per component: 1e-5 of the largest norm its
+    field (E or H) reaches during the run (checked every quarter of the run),
+    element-wise 5e-5 of the field's largest value.  At the end of the 128^3 run H
+    has fallen to a ninth of its peak (the pulse is over) and H1, the
+    component the x-directed dipole drives least, to 3 % of it: relative to
+    their own final norms the H components then differ by 8e-5 to 2.7e-4
+    (E: 3e-6), which is printed and bounded at 5e-4."""
+    cps = [steps // 4, steps // 2, 3 * steps // 4, steps]
+    r32 = _run_gpu_workload(Solver, name, "fp32_refine", cps)
+    r64 = _run_gpu_workload(Solver, name, "fp64", cps)
+    peak = [max(np.linalg.norm(g[f * 3:(f + 1) * 3].reshape(3, -1), axis=1).max()
+                for g, _ in r64) for f in range(2)]
+    peak_abs = [max(np.abs(g[f * 3:(f + 1) * 3]).max() for g, _ in r64) for f in range(2)]
+    for (g32, t32), (g64, t64), k in zip(r32, r64, cps):
+        assert t32 == pytest.approx(t64, rel=1e-12)
+        err = [np.linalg.norm(g32[c] - g64[c]) for c in range(6)]
+        own = [e / max(np.linalg.norm(g64[c]), 1e-300) for c, e in enumerate(err)]
+        to_peak = [e / peak[c // 3] for c, e in enumerate(err)]
+        emax = [np.abs(g32[c] - g64[c]).max() / peak_abs[c // 3] for c in range(6)]
+        print(name, k, "fp32 vs fp64: relative to the field's peak", to_peak,
+              "to the component's own norm", own, "max-abs to the field's peak", emax)
+        assert max(to_peak) <= TOL32, (k, to_peak)
+        assert max(own) <= 5e-4, (k, own)
+        assert max(emax) <= MAXABS_FACTOR32 * TOL32, (k, emax)
+
+
 def test_mms16_fp32_refine(Solver):
     w = workloads.make("mms16")
     prob = maxwell.Problem(w.N, w.p, 1.0, 1.0, 0.0, w.dt)
