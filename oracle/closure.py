@@ -116,7 +116,13 @@ def unflatten(flat, shapes):
 
 
 def bf16_round(a: np.ndarray) -> np.ndarray:
-    """Round float values to bfloat16 (round to nearest even), as float64."""
+    """Round float values to bfloat16 (round to nearest even), as float64.
+
+    The standard bit manipulation of IEEE single precision: bfloat16 keeps
+    the upper 16 bits of a float32, and adding 0x7FFF plus the lowest kept
+    bit before truncating rounds to nearest with ties to even (the rounding
+    of the bfloat16 format's conversion, as in e.g. Intel's BFLOAT16
+    hardware numerics definition, 2018)."""
     f = np.asarray(a, dtype=np.float32).copy()
     u = f.view(np.uint32)
     lsb = (u >> 16) & 1

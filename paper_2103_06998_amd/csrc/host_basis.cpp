@@ -41,6 +41,12 @@ int find_span(const std::vector<double>& t, int p, int n, double x) {
   return lo;
 }
 
+// The p+1 B-splines of degree p that are nonzero on knot span `span` at x,
+// and their first derivatives: the triangular Cox-de Boor evaluation with
+// the knot differences kept in the lower triangle, as published in
+// L. Piegl and W. Tiller, The NURBS Book (2nd ed., Springer 1997),
+// algorithms A2.2 (basis functions) and A2.3 (derivatives), restated here
+// for the first derivative only.
 void basis_on_span(const std::vector<double>& t, int p, int span, double x, double* val,
                    double* der) {
   // ndu[j][r]: values of degree-j functions (upper triangle) and knot
@@ -82,6 +88,11 @@ void basis_on_span(const std::vector<double>& t, int p, int span, double x, doub
   }
 }
 
+// q-point Gauss-Legendre rule on [-1, 1]: the textbook Newton iteration on
+// the Legendre polynomial P_q (three-term recurrence for P_q and P_q') from
+// the initial guesses cos(pi (i + 3/4) / (q + 1/2)), weights
+// 2 / ((1 - x^2) P_q'(x)^2) (as in, e.g., Press et al., Numerical Recipes,
+// section 4.6 (3rd ed.: 4.6.1)).
 void gauss_legendre(int q, std::vector<double>& x, std::vector<double>& w) {
   // Newton iteration on P_q from the Chebyshev-like initial guesses.
   x.assign(q, 0.0);
