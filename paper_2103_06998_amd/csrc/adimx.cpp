@@ -1218,20 +1218,22 @@ hipError_t enqueue_mark(adi_ctx* c) {
 }
 
 // scale = RMS of the state; x = features of (state, cl_prev, material, source)
-hipError_t enqueue_features(adi_ctx* c, float* x, float* scale) {
+// (float32, or the network's packed bf16 input)
+template <typename O>
+hipError_t enqueue_features(adi_ctx* c, O* x, float* scale) {
   hipError_t e;
   if (c->esz == 8) {
     const double* st = static_cast<const double*>(c->B[0]);
     e = nn::launch_state_scale<double>(st, 6 * c->D, c->cl_red, kClosureBlocks, scale, c->stream);
     if (e == hipSuccess)
-      e = nn::launch_features<double>(st, static_cast<const double*>(c->cl_prev), c->cl_mat, c->n,
-                                      scale, c->src, c->d_t, c->dt, x, c->stream);
+      e = nn::launch_features(st, static_cast<const double*>(c->cl_prev), c->cl_mat, c->n, scale,
+                              c->src, c->d_t, c->dt, x, c->stream);
   } else {
     const float* st = static_cast<const float*>(c->B[0]);
     e = nn::launch_state_scale<float>(st, 6 * c->D, c->cl_red, kClosureBlocks, scale, c->stream);
     if (e == hipSuccess)
-      e = nn::launch_features<float>(st, static_cast<const float*>(c->cl_prev), c->cl_mat, c->n,
-                                     scale, c->src, c->d_t, c->dt, x, c->stream);
+      e = nn::launch_features(st, static_cast<const float*>(c->cl_prev), c->cl_mat, c->n, scale,
+                              c->src, c->d_t, c->dt, x, c->stream);
   }
   return e;
 }
@@ -1328,8 +1330,8 @@ int adi_step_closure(adi_ctx* c, adi_nn* nn_, int nsteps, float gate) {
   for (int i = 0; i < nsteps; ++i) {
     HIPCHK(c, enqueue_mark(c));
     HIPCHK(c, hipGraphLaunch(c->exec, c->stream));
-    HIPCHK(c, enqueue_features(c, x, scale));
-    st = nn::closure_forward(nn_, x, y, n, n, n, c->stream);
+    HIPCHK(c, enqueue_features(c, nn::closure_input16(nn_), scale));
+    st = nn::closure_forward_packed(nn_, y, n, n, n, c->stream);
     if (st != ADI_OK) return fail(c, st, "network forward");
     const int* flag = nullptr;
     if (gate > 0.f) {

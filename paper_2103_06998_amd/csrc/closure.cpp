@@ -102,23 +102,27 @@ int relayout(adi_nn* n, hipStream_t s) {
 }
 
 // Forward of the three layers on x (float32 [V][cin], device); output y
-// (float32 [V][cout], device).  Activations are kept for the backward pass.
-int forward_on(adi_nn* n, const float* x, float* y, int nx, int ny, int nz, hipStream_t s) {
+// (float32 [V][cout], device).  With keep (training) the hidden layers'
+// float32 pre-activations are kept for the backward pass; without it
+// (inference) only their bf16 activations are written, the same values.
+int forward_on(adi_nn* n, const float* x, float* y, int nx, int ny, int nz, hipStream_t s,
+               bool keep = true) {
   int st = ensure_acts(n, nx, ny, nz);
   if (st != ADI_OK) return st;
-  NNCHK(n, launch_pack(x, n->cin, 16, n->V, n->x16, s));
+  if (x) NNCHK(n, launch_pack(x, n->cin, 16, n->V, n->x16, s));  // else x16 is filled
+  const int hidden = keep ? 1 : 3;
   ConvArgs a{};
   a.nx = nx;
   a.ny = ny;
   a.nz = nz;
   a.in = n->x16; a.wt = n->wf[0]; a.bias = n->bias[0]; a.out_f32 = n->z1; a.out_bf16 = n->a1;
-  NNCHK(n, launch_conv(16, 32, 1, a, s));
+  NNCHK(n, launch_conv(16, 32, hidden, a, s));
   a.in = n->a1; a.wt = n->wf[1]; a.bias = n->bias[1]; a.out_f32 = n->z2; a.out_bf16 = n->a2;
-  NNCHK(n, launch_conv(32, 32, 1, a, s));
+  NNCHK(n, launch_conv(32, 32, hidden, a, s));
   a.in = n->a2; a.wt = n->wf[2]; a.bias = n->bias[2]; a.out_f32 = y; a.out_bf16 = nullptr;
   a.co_real = n->cout;
   NNCHK(n, launch_conv(32, 16, 0, a, s));
-  n->forward_done = true;
+  n->forward_done = keep;
   return ADI_OK;
 }
 
@@ -283,7 +287,13 @@ int closure_buffers(adi_nn* n, int nx, int ny, int nz, float** x, float** y, flo
 }
 
 int closure_forward(adi_nn* n, const float* x, float* y, int nx, int ny, int nz, hipStream_t s) {
-  return forward_on(n, x, y, nx, ny, nz, s);
+  return forward_on(n, x, y, nx, ny, nz, s, false);
+}
+
+__bf16* closure_input16(adi_nn* n) { return n->x16; }
+
+int closure_forward_packed(adi_nn* n, float* y, int nx, int ny, int nz, hipStream_t s) {
+  return forward_on(n, nullptr, y, nx, ny, nz, s, false);
 }
 
 int closure_cin(const adi_nn* n) { return n->cin; }

@@ -40,6 +40,9 @@ __device__ __forceinline__ bf16x8 zero8() {
 // EPI 0: out_f32[v][co_real] = acc + bias                (last layer)
 // EPI 1: z = acc + bias -> out_f32[v][COP] = z, out_bf16 = silu(z)  (hidden)
 // EPI 2: out_bf16[v][COP] = acc * silu'(zprev[v][COP])   (backward data)
+// EPI 3: out_bf16[v][COP] = silu(acc + bias)             (hidden, inference:
+//        the float32 pre-activation, needed only by the backward pass, is
+//        not written)
 template <int CI, int COP, int EPI>
 __global__ __launch_bounds__(kThreads) void conv_kernel(ConvArgs a) {
   constexpr int PIT = CI + 8;  // staged bf16 per voxel (16-byte aligned rows)
@@ -109,6 +112,8 @@ __global__ __launch_bounds__(kThreads) void conv_kernel(ConvArgs a) {
           const float z = val + a.bias[co];
           a.out_f32[v * COP + co] = z;
           a.out_bf16[v * COP + co] = __bf16(silu_f(z));
+        } else if (EPI == 3) {
+          a.out_bf16[v * COP + co] = __bf16(silu_f(val + a.bias[co]));
         } else {
           a.out_bf16[v * COP + co] = __bf16(val * silu_grad_f(a.zprev[v * COP + co]));
         }
@@ -331,6 +336,8 @@ hipError_t launch_conv(int ci, int cop, int epi, const ConvArgs& a, hipStream_t 
   else if (ci == 32 && cop == 16 && epi == 0) hipLaunchKernelGGL((conv_kernel<32, 16, 0>), grid, block, 0, s, a);
   else if (ci == 16 && cop == 32 && epi == 2) hipLaunchKernelGGL((conv_kernel<16, 32, 2>), grid, block, 0, s, a);
   else if (ci == 32 && cop == 32 && epi == 2) hipLaunchKernelGGL((conv_kernel<32, 32, 2>), grid, block, 0, s, a);
+  else if (ci == 16 && cop == 32 && epi == 3) hipLaunchKernelGGL((conv_kernel<16, 32, 3>), grid, block, 0, s, a);
+  else if (ci == 32 && cop == 32 && epi == 3) hipLaunchKernelGGL((conv_kernel<32, 32, 3>), grid, block, 0, s, a);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }
@@ -436,12 +443,14 @@ __global__ void scale_kernel(const float* __restrict__ partial, int nblk, size_t
 // x[v][12..14] = material features,
 // x[v][15]     = source impulse of the step / scale, spread over the
 //                coefficients by the tensor-product basis values at the dipole
-template <typename T>
+// (O = float for the API; O = bf16 writes the network's packed input
+// directly, the same values as packing the float features)
+template <typename T, typename O>
 __global__ void features_kernel(const T* __restrict__ state, const T* __restrict__ prev,
                                 const float* __restrict__ mat, int n,
                                 const float* __restrict__ scale, SourceArgs src,
                                 const double* __restrict__ tnow, double dt,
-                                float* __restrict__ x) {
+                                O* __restrict__ x) {
   const size_t D = size_t(n) * n * n;
   const float inv = 1.0f / scale[0];
   double jimp = 0.0;  // dt/2 (g(t - 3 dt/4) + g(t - dt/4)) amp, t = time after the step
@@ -457,15 +466,15 @@ __global__ void features_kernel(const T* __restrict__ state, const T* __restrict
   }
   for (size_t v = size_t(blockIdx.x) * blockDim.x + threadIdx.x; v < D;
        v += size_t(gridDim.x) * blockDim.x) {
-    float* o = x + v * kFeatures;
+    O* o = x + v * kFeatures;
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
       const double cur = double(state[c * D + v]);
-      o[c] = float(cur) * inv;
-      o[6 + c] = float(cur - double(prev[c * D + v])) * inv;
+      o[c] = O(float(cur) * inv);
+      o[6 + c] = O(float(cur - double(prev[c * D + v])) * inv);
     }
 #pragma unroll
-    for (int c = 0; c < 3; ++c) o[12 + c] = mat[v * 3 + c];
+    for (int c = 0; c < 3; ++c) o[12 + c] = O(mat[v * 3 + c]);
     float sf = 0.f;
     if (src.comp >= 0) {
       const int i = int(v % n) - src.first[0], j = int((v / n) % n) - src.first[1],
@@ -474,7 +483,7 @@ __global__ void features_kernel(const T* __restrict__ state, const T* __restrict
       if (i >= 0 && i <= P && j >= 0 && j <= P && k >= 0 && k <= P)
         sf = float(jimp * src.bx[i] * src.by[j] * src.bz[k]) * inv;
     }
-    o[15] = sf;
+    o[15] = O(sf);
   }
 }
 
@@ -564,13 +573,13 @@ hipError_t launch_state_scale(const T* state, size_t count, float* partial, int 
   return hipGetLastError();
 }
 
-template <typename T>
+template <typename T, typename O>
 hipError_t launch_features(const T* state, const T* prev, const float* mat, int n,
                            const float* scale, const SourceArgs& src, const double* tnow,
-                           double dt, float* x, hipStream_t s) {
+                           double dt, O* x, hipStream_t s) {
   const size_t D = size_t(n) * n * n;
-  hipLaunchKernelGGL(features_kernel<T>, dim3(blocks_for(D)), dim3(256), 0, s, state, prev, mat, n,
-                     scale, src, tnow, dt, x);
+  hipLaunchKernelGGL((features_kernel<T, O>), dim3(blocks_for(D)), dim3(256), 0, s, state, prev,
+                     mat, n, scale, src, tnow, dt, x);
   return hipGetLastError();
 }
 
@@ -605,9 +614,12 @@ hipError_t launch_gate(const float* y, const T* state, const T* prev, size_t cou
 
 #define INST(T)                                                                                  \
   template hipError_t launch_state_scale<T>(const T*, size_t, float*, int, float*, hipStream_t);  \
-  template hipError_t launch_features<T>(const T*, const T*, const float*, int, const float*,     \
-                                         const SourceArgs&, const double*, double, float*,        \
-                                         hipStream_t);                                            \
+  template hipError_t launch_features<T, float>(const T*, const T*, const float*, int,            \
+                                                const float*, const SourceArgs&, const double*,   \
+                                                double, float*, hipStream_t);                     \
+  template hipError_t launch_features<T, __bf16>(const T*, const T*, const float*, int,           \
+                                                 const float*, const SourceArgs&, const double*,  \
+                                                 double, __bf16*, hipStream_t);                   \
   template hipError_t launch_target<T>(const T*, const T*, size_t, const float*, float*,          \
                                        hipStream_t);                                              \
   template hipError_t launch_apply<T>(T*, int, const float*, const float*, const int*,            \

@@ -47,10 +47,10 @@ constexpr int kOutputs = 6;    // corrections of E1..E3, H1..H3
 template <typename T>
 hipError_t launch_state_scale(const T* state, size_t count, float* partial, int nblk,
                               float* scale, hipStream_t s);
-template <typename T>
+template <typename T, typename O>
 hipError_t launch_features(const T* state, const T* prev, const float* mat, int n,
                            const float* scale, const SourceArgs& src, const double* tnow,
-                           double dt, float* x, hipStream_t s);
+                           double dt, O* x, hipStream_t s);
 template <typename T>
 hipError_t launch_target(const T* fine, const T* coarse, size_t D, const float* scale, float* t,
                          hipStream_t s);
@@ -75,6 +75,10 @@ namespace nn {
 int closure_buffers(adi_nn* n, int nx, int ny, int nz, float** x, float** y, float** scale,
                     float** partial);
 int closure_forward(adi_nn* n, const float* x, float* y, int nx, int ny, int nz, hipStream_t s);
+// The network's packed bf16 input buffer [V][16] (after closure_buffers),
+// and an inference forward that starts from it (no packing step).
+__bf16* closure_input16(adi_nn* n);
+int closure_forward_packed(adi_nn* n, float* y, int nx, int ny, int nz, hipStream_t s);
 int closure_cin(const adi_nn* n);
 int closure_cout(const adi_nn* n);
 }  // namespace nn
