@@ -91,11 +91,16 @@ def kernel_key(launch, nth, n, p, precision, res64=RES64_DEFAULT):
     m = (n + S - 1) // S      # rows per segment
     MR = next(r for r in (24, 36, 48) if m <= r)
     mod = "true" if launch["nmod"] else "false"
+    if k == "apply_xyz":  # H stage: apply-and-solve lines (partitioned solves only)
+        if launch["ncomp"] == 3:
+            return f"spike_mixed_kernel<{T}, {p}, {MR}, {S}, true>"
+        xax = "true" if launch["ncomp"] == 1 else "false"
+        return f"spike_kernel<{T}, {p}, {xax}, {MR}, {S}, true>"
     if k == "sweep_xyz":
-        return f"spike_mixed_kernel<{T}, {p}, {MR}, {S}>" if spike else \
+        return f"spike_mixed_kernel<{T}, {p}, {MR}, {S}, false>" if spike else \
             f"sweep_mixed_kernel<{T}, {p}, {mod}>"
     xax = "true" if k == "sweep_x" else "false"
-    return f"spike_kernel<{T}, {p}, {xax}, {MR}, {S}>" if spike else \
+    return f"spike_kernel<{T}, {p}, {xax}, {MR}, {S}, false>" if spike else \
         f"sweep_kernel<{T}, {p}, {xax}, {mod}>"
 
 

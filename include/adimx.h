@@ -173,8 +173,11 @@ int adi_set_source(adi_ctx* ctx, const double xs[3], int comp, double amp, doubl
                    double t0, double width);
 
 /* Upload a state (6 D float64, layout above: E^n and H^n of the scheme of
- * section "Alternating directions splitting for Maxwell equations", with the
- * PEC-constrained coefficients expected to be zero) and set the time t.
+ * section "Alternating directions splitting for Maxwell equations") and set
+ * the time t.  The state lives in the space with the PEC conditions imposed
+ * strongly: the coefficients of E_c on the faces normal to the two other
+ * axes and of H_c on the faces normal to axis c are set to zero (the step
+ * assumes so; a state written through adi_fields_device must satisfy it).
  * Copied; waits for the context's stream; ENONFINITE for a value that is not
  * finite. */
 int adi_set_fields(adi_ctx* ctx, const double* EH, double t);

@@ -71,6 +71,10 @@ struct adi_ctx {
   // float32 mode: stages whose increment is formed in float64 arithmetic
   // (bit res64_bit(stage, sub)); the others use float32 arithmetic
   int res64 = ADI_RES64_DEFAULT;
+  // H stage as two apply-and-solve line rounds (delta = dt / (2 mu) the same
+  // in every row; set by adi_factor)
+  bool fast_h = false;
+  double hdelta = 0.0;
   bool factored = false;
 
   unsigned char* ws = nullptr;
@@ -236,7 +240,7 @@ int pick_zchunk(const int* ns) {
 
 // ---------------------------------------------------------------- enqueue
 enum LaunchKind { kKindRhsE = 0, kKindRhsH = 1, kKindResidual = 2, kKindSweepX = 3, kKindSweepYZ = 4,
-                  kKindSweepXYZ = 5 };
+                  kKindSweepXYZ = 5, kKindApply = 6 };
 
 // Run `launch` on stream s; when profiling, bracket it with two events.
 template <typename F>
@@ -442,6 +446,97 @@ hipError_t enqueue_solves(adi_ctx* c, int kindH, int sub, void* buf, const void*
   return hipSuccess;
 }
 
+// H stage of substep `sub` with one delta = dt / (2 mu) in every row
+// (discrete2 / discrete4).  Each H_c has two curl terms, delta (+-) times
+// E_b with the advection matrix A along one axis a != c and M along the
+// other two.  Since E_b vanishes on the faces normal to c (PEC) and H_c
+// vanishes there too, the mass solve along c and along the third axis
+// cancel their M factors exactly, and the Kronecker solve of the term
+// reduces to M_a^{-1} A_a along its own axis:
+//   H_c' = H_c + sum over the two terms of (+-delta) M_a^{-1} (A_a E_b).
+// Two rounds of apply-and-solve line launches (one term per component each,
+// the three components on three different axes) replace the right-hand
+// side kernel and the three rounds of mass solves.
+template <typename T>
+hipError_t enqueue_h_fast(adi_ctx* c, int sub, void* Ein, void* Eout, void* Hin, void* Hout,
+                          hipStream_t s) {
+  struct Term { int axis, sign, b; bool old; };  // b = E component, old = E before the stage
+  static const Term terms[2][3][2] = {
+      {{{1, -1, 2, true}, {2, +1, 1, false}},
+       {{2, -1, 0, true}, {0, +1, 2, false}},
+       {{0, -1, 1, true}, {1, +1, 0, false}}},
+      {{{2, +1, 1, true}, {1, -1, 2, false}},
+       {{0, +1, 2, true}, {2, -1, 0, false}},
+       {{1, +1, 0, true}, {0, -1, 1, false}}}};
+  const int W = 2 * c->p + 1;
+  for (int k = 0; k < 2; ++k) {
+    SweepDesc d[3];
+    for (int ci = 0; ci < 3; ++ci) {
+      const Term& t = terms[sub - 1][ci][k];
+      const int ax = t.axis, n = c->ns[ax];
+      void* io = comp(Hout, ci, c);
+      SweepDesc q = desc_for(c, 1, sub, ci, ax, comp(t.old ? Ein : Eout, t.b, c), io,
+                             k == 0 ? comp(Hin, ci, c) : io);
+      q.aband = static_cast<const T*>(c->bandT[ax]) + size_t(1) * n * W;  // op 1 = A
+      q.scale = t.sign * c->hdelta;
+      d[ax] = q;  // one term per axis in each round
+    }
+    SweepArgs a{};
+    for (int q = 0; q < 3; ++q) a.d[q] = d[q];  // x descriptor first
+    for (int q = 0; q < 3; ++q) a.dim[q] = c->ns[q];
+    a.apply = 1;
+    a.xaxis = 2;
+    a.spike = spike_for(a, 3);
+    if (!a.spike) return hipErrorInvalidValue;
+    if (sub == 2 && k == 1) {
+      a.tick_t = c->d_t;
+      a.tick_dt = c->dt;
+    }
+    const size_t blocks = line_blocks(c, a.d, 3) * 3;
+    if (blocks <= 1024) {
+      hipError_t e = timed(c, s, kKindApply, 3, 0, 3,
+                           [&] { return launch_sweep<T>(c->p, 3, a, s); });
+      if (e != hipSuccess) return e;
+      continue;
+    }
+    // larger rounds: the x lines on the side branch, the y/z lines here
+    SweepArgs ax_{}, ayz{};
+    ax_.d[0] = d[0];
+    ayz.d[0] = d[1];
+    ayz.d[1] = d[2];
+    for (SweepArgs* g : {&ax_, &ayz}) {
+      for (int q = 0; q < 3; ++q) g->dim[q] = c->ns[q];
+      g->apply = 1;
+    }
+    ax_.xaxis = 1;
+    ayz.xaxis = 0;
+    ax_.spike = spike_for(ax_, 1);
+    ayz.spike = spike_for(ayz, 2);
+    ayz.tick_t = a.tick_t;
+    ayz.tick_dt = a.tick_dt;
+    const bool branch = !c->profiling && c->side;
+    hipEvent_t ev = nullptr;
+    if (branch) {
+      hipError_t e = next_event(c, &ev);
+      if (e == hipSuccess) e = hipEventRecord(ev, s);
+      if (e == hipSuccess) e = hipStreamWaitEvent(c->side, ev, 0);
+      if (e != hipSuccess) return e;
+    }
+    hipStream_t xs = branch ? c->side : s;
+    hipError_t e = timed(c, xs, kKindApply, 1, 0, 1, [&] { return launch_sweep<T>(c->p, 1, ax_, xs); });
+    if (e == hipSuccess)
+      e = timed(c, s, kKindApply, 2, 0, 2, [&] { return launch_sweep<T>(c->p, 2, ayz, s); });
+    if (e != hipSuccess) return e;
+    if (branch) {
+      e = next_event(c, &ev);
+      if (e == hipSuccess) e = hipEventRecord(ev, c->side);
+      if (e == hipSuccess) e = hipStreamWaitEvent(s, ev, 0);
+      if (e != hipSuccess) return e;
+    }
+  }
+  return hipSuccess;
+}
+
 template <typename T>
 hipError_t enqueue_step_t(adi_ctx* c, hipStream_t s) {
   void* const* B = c->B;
@@ -483,7 +578,10 @@ hipError_t enqueue_step_t(adi_ctx* c, hipStream_t s) {
       if (e != hipSuccess) return e;
     }
     // H stage
-    {
+    if (c->fast_h) {
+      hipError_t e = enqueue_h_fast<T>(c, sub, Ein, Eout, Hin, Hout, s);
+      if (e != hipSuccess) return e;
+    } else {
       const void* f[9] = {comp(Hin, 0, c),  comp(Hin, 1, c),  comp(Hin, 2, c),
                           comp(Ein, 0, c),  comp(Ein, 1, c),  comp(Ein, 2, c),
                           comp(Eout, 0, c), comp(Eout, 1, c), comp(Eout, 2, c)};
@@ -954,6 +1052,15 @@ int adi_factor(adi_ctx* c, double dt) {
   if (!(worst > c->pivot_floor))
     return fail(c, ADI_ESINGULAR, "pivot at or below the floor in a material-modified factor");
 
+  // the H stage's shortcut needs one delta for all rows and partitioned
+  // solves with one segment count on every axis
+  bool one_delta = true;
+  for (size_t i = 1; i < D && one_delta; ++i) one_delta = co[3][i] == co[3][0];
+  c->fast_h = one_delta && c->spike_ok[0] && c->spike_ok[1] && c->spike_ok[2] &&
+              spike_segments(c->ns[0]) == spike_segments(c->ns[1]) &&
+              spike_segments(c->ns[0]) == spike_segments(c->ns[2]);
+  c->hdelta = co[3][0];
+
   st = capture(c);
   if (st != ADI_OK) return st;
   c->factored = true;
@@ -985,10 +1092,26 @@ int adi_set_fields(adi_ctx* c, const double* EH, double t) {
     if (st != ADI_OK) return st;
   }
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  // the state lives in the constrained space: E_c is zero on the faces
+  // normal to the two other axes, H_c on the faces normal to axis c (PEC,
+  // imposed strongly)
+  std::vector<double> v(EH, EH + 6 * c->D);
+  const int nx = c->ns[0], ny = c->ns[1], nz = c->ns[2];
+  for (int f = 0; f < 6; ++f) {
+    const int cc = f % 3;
+    double* a = v.data() + size_t(f) * c->D;
+    for (int k = 0; k < nz; ++k)
+      for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+          const bool b[3] = {i == 0 || i == nx - 1, j == 0 || j == ny - 1, k == 0 || k == nz - 1};
+          const bool zero = f < 3 ? (b[(cc + 1) % 3] || b[(cc + 2) % 3]) : b[cc];
+          if (zero) a[(size_t(k) * ny + j) * nx + i] = 0.0;
+        }
+  }
   if (c->esz == 8) {
-    HIPCHK(c, hipMemcpy(c->B[0], EH, 6 * c->D * 8, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->B[0], v.data(), 6 * c->D * 8, hipMemcpyHostToDevice));
   } else {
-    std::vector<float> f(EH, EH + 6 * c->D);
+    std::vector<float> f(v.begin(), v.end());
     HIPCHK(c, hipMemcpy(c->B[0], f.data(), f.size() * 4, hipMemcpyHostToDevice));
   }
   HIPCHK(c, hipMemcpy(c->d_t, &t, 8, hipMemcpyHostToDevice));

@@ -107,6 +107,9 @@ struct SweepDesc {
                           // as [r*P + k] / [r], then R, q x q), or null
   int segs;               // segments per line of spk (spike_segments(n))
   int modified;           // 0 = shared factors, 1 = per-line factors
+  const void* aband;      // SweepArgs::apply: band [r][2p+1] of the 1D operator applied
+                          // to `in` before the solve (T)
+  double scale;           // SweepArgs::apply: out = acc + scale * solution
 };
 
 struct SweepArgs {
@@ -118,6 +121,8 @@ struct SweepArgs {
                           // 2: both, descriptors of x lines first
   int spike;              // 0, or the segments per line (every descriptor's segs) of
                           // the partitioned solve of shared-factor lines
+  int apply;              // 1: each line solves M x = A in (A = the descriptor's aband;
+                          // partitioned solve only) and stores acc + scale * x
   double* tick_t;         // if non-null, block (0,0) thread 0 does *tick_t += tick_dt
   double tick_dt;
 };

@@ -884,9 +884,14 @@ __device__ __forceinline__ void sweep_body(const SweepArgs& a) {
 //   3. x = g - V T - W U with the precomputed spikes V, W.
 // The factors, spikes and R of the descriptor are staged in LDS (broadcast
 // reads: every lane of a wave reads the same row).
-template <typename T, int P, bool XAX, int MR, int S>
+// With AP the right-hand side is A v for the line's values v (A = the
+// descriptor's banded operator, staged in LDS behind R): each segment loads
+// its rows with a p-row halo on both sides and forms its rows of A v before
+// the solve, and the store writes acc + scale * x.
+template <typename T, int P, bool XAX, int MR, int S, bool AP>
 __device__ __forceinline__ void spike_body(const SweepArgs& a) {
-  constexpr int Q = 2 * P * (S - 1);
+  constexpr int Q = 2 * P * (S - 1), W = 2 * P + 1;
+  constexpr int MRV = AP ? MR + 2 * P : MR;  // rows of the line a segment loads
   extern __shared__ __align__(16) unsigned char smem[];
   T* sf = reinterpret_cast<T*>(smem);
   const SweepDesc& ds = a.d[blockIdx.y];
@@ -895,7 +900,8 @@ __device__ __forceinline__ void spike_body(const SweepArgs& a) {
   const int n = a.dim[ds.axis];                                   // rows per line
   const int nl = int(nxy * size_t(a.dim[2]) / size_t(n));         // lines
   if (int(blockIdx.x) * 64 >= nl) return;  // block-uniform: before any barrier
-  const int nf = n * (4 * P + 1) + Q * Q;
+  const int nf0 = n * (4 * P + 1) + Q * Q;
+  const int nf = nf0 + (AP ? n * W : 0);
   T* gex = sf + nf;  // [Q][64] boundary values of g
   // the segment is the wave: wave-uniform, so its row offsets stay scalar
   const int tid = threadIdx.x, seg = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
@@ -933,22 +939,29 @@ __device__ __forceinline__ void spike_body(const SweepArgs& a) {
   // in order, so the tile needs no barrier.
   T* xt = gex + Q * 64 + seg * (8 * 65);
   const int l0 = blockIdx.x * 64;
-  T y[MR];
-  if (XAX && MR <= 40) {
+  // line row held in load slot r: the segment's rows (slots past it repeat
+  // its last row), or with AP the segment's rows with a p-row halo on both
+  // sides, clamped to the line (the band of A is zero outside the line)
+  const int mv = AP ? m + 2 * P : m;
+  auto rowof = [&](int r) {
+    return AP ? min(max(b0 - P + r, 0), n - 1) : b0 + min(r, m - 1);
+  };
+  T yv[MRV];
+  if (XAX && (AP ? MRV <= 48 : MR <= 40)) {
     // short segments: every chunk's loads in flight at once (rows clamped),
     // then the chunks go through the tile one by one
-    constexpr int NC = (MR + 7) / 8;
+    constexpr int NC = (MRV + 7) / 8;
     T v[NC][8];
 #pragma unroll
     for (int c = 0; c < NC; ++c)
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         const int e = lane + 64 * j, ln = e >> 3, rr = e & 7;
-        v[c][j] = in[size_t(min(l0 + ln, nl - 1)) * n + b0 + min(8 * c + rr, m - 1)];
+        v[c][j] = in[size_t(min(l0 + ln, nl - 1)) * n + rowof(8 * c + rr)];
       }
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-      if (8 * c < m) {  // uniform
+      if (8 * c < mv) {  // uniform
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
           const int e = lane + 64 * j;
@@ -957,19 +970,19 @@ __device__ __forceinline__ void spike_body(const SweepArgs& a) {
         __builtin_amdgcn_wave_barrier();
 #pragma unroll
         for (int rr = 0; rr < 8; ++rr)
-          if (8 * c + rr < MR) y[8 * c + rr] = xt[rr * 65 + lane];
+          if (8 * c + rr < MRV) yv[8 * c + rr] = xt[rr * 65 + lane];
         __builtin_amdgcn_wave_barrier();
       }
     }
   } else if (XAX) {
 #pragma unroll
-    for (int c0 = 0; c0 < MR; c0 += 8) {
-      if (c0 < m) {  // uniform
+    for (int c0 = 0; c0 < MRV; c0 += 8) {
+      if (c0 < mv) {  // uniform
         T v[8];
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
           const int e = lane + 64 * j, ln = e >> 3, rr = e & 7;
-          v[j] = in[size_t(min(l0 + ln, nl - 1)) * n + b0 + min(c0 + rr, m - 1)];
+          v[j] = in[size_t(min(l0 + ln, nl - 1)) * n + rowof(c0 + rr)];
         }
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
@@ -979,16 +992,34 @@ __device__ __forceinline__ void spike_body(const SweepArgs& a) {
         __builtin_amdgcn_wave_barrier();
 #pragma unroll
         for (int rr = 0; rr < 8; ++rr)
-          if (c0 + rr < MR) y[c0 + rr] = xt[rr * 65 + lane];
+          if (c0 + rr < MRV) yv[c0 + rr] = xt[rr * 65 + lane];
         __builtin_amdgcn_wave_barrier();
       }
     }
   } else {
 #pragma unroll
-    for (int r = 0; r < MR; ++r) y[r] = in[lbase + size_t(b0 + min(r, m - 1)) * rstride];
+    for (int r = 0; r < MRV; ++r) yv[r] = in[lbase + size_t(rowof(r)) * rstride];
   }
-  stage_batched<T, 64 * S>(sf, static_cast<const T*>(ds.spk), nf, tid);
+  stage_batched<T, 64 * S>(sf, static_cast<const T*>(ds.spk), nf0, tid);
+  if constexpr (AP) stage_batched<T, 64 * S>(sf + nf0, static_cast<const T*>(ds.aband), n * W, tid);
   __syncthreads();  // factors staged
+  T y[MR];
+  if constexpr (AP) {
+    // rows of A v: padding rows (r >= m) read band rows past the line, which
+    // lie inside the block's LDS; their results are never stored
+    const T* sA = sf + nf0;
+#pragma unroll
+    for (int r = 0; r < MR; ++r) {
+      const T* Ar = sA + (b0 + r) * W;
+      T acc = T(0);
+#pragma unroll
+      for (int d = 0; d < W; ++d) acc += Ar[d] * yv[r + d];
+      y[r] = acc;
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < MR; ++r) y[r] = yv[r];
+  }
 
   // Forward and backward recurrences over all MR rows without a branch per
   // row, so that the compiler issues the factor reads of later rows (at
@@ -1084,6 +1115,11 @@ __device__ __forceinline__ void spike_body(const SweepArgs& a) {
       }
     }
   }
+  if constexpr (AP) {
+    const T sc = T(ds.scale);
+#pragma unroll
+    for (int r = 0; r < MR; ++r) y[r] *= sc;
+  }
   if (XAX) {
 #pragma unroll
     for (int c0 = 0; c0 < MR; c0 += 8) {
@@ -1137,14 +1173,14 @@ __global__ __launch_bounds__(64) void sweep_mixed_kernel(SweepArgs a) {
   if (a.d[blockIdx.y].axis == 0) sweep_body<T, P, true, MOD>(a);
   else sweep_body<T, P, false, MOD>(a);
 }
-template <typename T, int P, bool XAX, int MR, int S>
+template <typename T, int P, bool XAX, int MR, int S, bool AP>
 __global__ __launch_bounds__(64 * S) void spike_kernel(SweepArgs a) {
-  spike_body<T, P, XAX, MR, S>(a);
+  spike_body<T, P, XAX, MR, S, AP>(a);
 }
-template <typename T, int P, int MR, int S>
+template <typename T, int P, int MR, int S, bool AP>
 __global__ __launch_bounds__(64 * S) void spike_mixed_kernel(SweepArgs a) {
-  if (a.d[blockIdx.y].axis == 0) spike_body<T, P, true, MR, S>(a);
-  else spike_body<T, P, false, MR, S>(a);
+  if (a.d[blockIdx.y].axis == 0) spike_body<T, P, true, MR, S, AP>(a);
+  else spike_body<T, P, false, MR, S, AP>(a);
 }
 
 // ------------------------------------------------------------ factorisation
@@ -1319,39 +1355,45 @@ hipError_t launch_sweep_mixed(int ndesc, const SweepArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <typename T, int P, bool XAX, int MR, int S>
+template <typename T, int P, bool XAX, int MR, int S, bool AP>
 hipError_t launch_spike_k(int ndesc, const SweepArgs& a, hipStream_t s) {
   constexpr int Q = 2 * P * (S - 1);
   const LaunchShape sh = launch_shape(ndesc, a);
-  const size_t lds = (size_t(sh.nmax) * (4 * P + 1) + Q * Q + size_t(Q) * 64 +
-                      (XAX ? size_t(S) * 8 * 65 : 0)) * sizeof(T);
+  const size_t lds = (size_t(sh.nmax) * (4 * P + 1 + (AP ? 2 * P + 1 : 0)) + Q * Q +
+                      size_t(Q) * 64 + (XAX ? size_t(S) * 8 * 65 : 0)) * sizeof(T);
   dim3 grid((sh.lines + 63) / 64, ndesc);
-  auto k = spike_kernel<T, P, XAX, MR, S>;
+  auto k = spike_kernel<T, P, XAX, MR, S, AP>;
   hipError_t e = set_lds(k, lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k, grid, dim3(64 * S), lds, s, a);
   return hipGetLastError();
 }
 
-template <typename T, int P, int MR, int S>
+template <typename T, int P, int MR, int S, bool AP>
 hipError_t launch_spike_mixed_k(int ndesc, const SweepArgs& a, hipStream_t s) {
   constexpr int Q = 2 * P * (S - 1);
   const LaunchShape sh = launch_shape(ndesc, a);
-  const size_t lds = (size_t(sh.nmax) * (4 * P + 1) + Q * Q + size_t(Q) * 64 +
-                      size_t(S) * 8 * 65) * sizeof(T);
+  const size_t lds = (size_t(sh.nmax) * (4 * P + 1 + (AP ? 2 * P + 1 : 0)) + Q * Q +
+                      size_t(Q) * 64 + size_t(S) * 8 * 65) * sizeof(T);
   dim3 grid((sh.lines + 63) / 64, ndesc);
-  auto k = spike_mixed_kernel<T, P, MR, S>;
+  auto k = spike_mixed_kernel<T, P, MR, S, AP>;
   hipError_t e = set_lds(k, lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k, grid, dim3(64 * S), lds, s, a);
   return hipGetLastError();
+}
+
+template <typename T, int P, int MR, int S, bool AP>
+hipError_t launch_spike_xsa(int xaxis, int ndesc, const SweepArgs& a, hipStream_t s) {
+  if (xaxis == 2) return launch_spike_mixed_k<T, P, MR, S, AP>(ndesc, a, s);
+  return xaxis ? launch_spike_k<T, P, true, MR, S, AP>(ndesc, a, s)
+               : launch_spike_k<T, P, false, MR, S, AP>(ndesc, a, s);
 }
 
 template <typename T, int P, int MR, int S>
 hipError_t launch_spike_xs(int xaxis, int ndesc, const SweepArgs& a, hipStream_t s) {
-  if (xaxis == 2) return launch_spike_mixed_k<T, P, MR, S>(ndesc, a, s);
-  return xaxis ? launch_spike_k<T, P, true, MR, S>(ndesc, a, s)
-               : launch_spike_k<T, P, false, MR, S>(ndesc, a, s);
+  return a.apply ? launch_spike_xsa<T, P, MR, S, true>(xaxis, ndesc, a, s)
+                 : launch_spike_xsa<T, P, MR, S, false>(xaxis, ndesc, a, s);
 }
 
 // xaxis: 0 = y/z lines, 1 = x lines, 2 = both (descriptor axis per block)
@@ -1379,8 +1421,10 @@ hipError_t launch_sweep_p(int ndesc, const SweepArgs& a, hipStream_t s) {
   const bool mod = a.d[0].modified != 0;
   for (int i = 1; i < ndesc; ++i)
     if ((a.d[i].modified != 0) != mod) return hipErrorInvalidValue;
+  if (a.apply && (!a.spike || mod)) return hipErrorInvalidValue;  // partitioned solve only
   if (a.spike && !mod) {
     for (int i = 0; i < ndesc; ++i) {
+      if (a.apply && !a.d[i].aband) return hipErrorInvalidValue;
       const int n = a.dim[a.d[i].axis];
       if (!a.d[i].spk || a.d[i].segs != a.spike || spike_segments(n) != a.spike ||
           n < kSpikeMinN || n > kSpikeMaxN)

@@ -226,6 +226,37 @@ def test_fp32_residual_arithmetic_choices(Solver, N, res64):
     print("fp32 residual mask", res64, N, "errors", errs)
 
 
+@pytest.mark.parametrize("N,p,precision,steps", [(45, 3, "fp64", 2), (45, 3, "fp32_refine", 2),
+                                                  (62, 2, "fp64", 2), (146, 2, "fp64", 1),
+                                                  (196, 2, "fp32_refine", 1), (128, 3, "fp64", 1)])
+def test_constant_mu_h_stage_shortcut(Solver, N, p, precision, steps):
+    """With one permeability everywhere (delta = dt/(2 mu) the same in every
+    row) the H stage runs as two rounds of apply-and-solve lines
+    (H_c' = H_c +- delta M_a^-1 A_a E_b per curl term) instead of the
+    right-hand side and three mass-solve rounds; random eps and sigma, a
+    source, against the oracle's full Kronecker solve.  n = 48 and 64:
+    mixed-axis rounds; n = 148: rounds split into concurrent x and y/z
+    launches; n = 198: eight segments per line; n = 131: the benchmark's
+    lines."""
+    eps, _, sig, src = random_setup(N, p, seed=300 + N)
+    mu = np.full_like(eps, 1.3)
+    dt = 0.5 / N
+    prob = maxwell.Problem(N, p, eps, mu, sig, dt, src)
+    s = make_gpu(Solver, N, p, eps, mu, sig, dt, src, precision)
+    E, H = constrained_random_state(prob, 23)
+    s.set_fields(np.stack(E + H), 0.03)
+    s.step(steps)
+    E2, H2, t2 = prob.run(E, H, 0.03, steps)
+    got, tg = s.get_fields()
+    assert tg == pytest.approx(t2, rel=1e-12)
+    compare_state(got, E2, H2, TOL64 if precision == "fp64" else TOL32,
+                  ("h shortcut", N, p, precision))
+    s.profile(1)
+    kinds = [L["kind"] for L in s.profile_read()]
+    assert "rhs_H" not in kinds and "apply_xyz" in kinds, kinds
+    s.close()
+
+
 class Float32Storage(maxwell.Problem):
     """The oracle with its state rounded to float32 where the float32 mode
     stores it (the E components after the E stage, before the H stage reads

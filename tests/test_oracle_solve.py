@@ -328,3 +328,50 @@ def test_local_time_step_equals_dense_block_solve():
     a2, b2, _ = loc.step(E, H, 0.05)
     for x, y in zip(a1 + b1, a2 + b2):
         assert np.array_equal(x, y)
+
+
+def _h_by_line_operators(prob, sub, fields, c):
+    """H_c after the H stage written as H_c plus, per curl term of discrete2 /
+    discrete4, (+-delta) M_a^{-1} (A_a E_b) along the term's own axis a (the
+    mass factors of the two other axes cancelled), with delta taken from the
+    first row: valid when delta is one constant."""
+    H = fields[f"H{c + 1}"].copy()
+    delta = prob.coef["delta"].flat[0]
+    for coef, sign, f, ops in maxwell.H_TERMS[sub][c]:
+        if coef == "one":
+            continue
+        a = ops.index("A")
+        ax = maxwell._NP_AXIS[a]
+        u = banded.apply_axis(fields[f], prob.axis_ops[a]["A"], ax, prob.p)
+        H += sign * delta * banded.solve_axis(u, ax, prob.axis_ops[a]["M"], prob.p)
+    return H
+
+
+@pytest.mark.parametrize("N,p", [(4, 2), (5, 3), ((3, 4, 6), 2)])
+def test_constant_mu_h_stage_is_one_line_operator_per_term(N, p):
+    """With one permeability the H stage's Kronecker solve of each curl term
+    reduces to M_a^{-1} A_a along the term's axis, because the constrained
+    state vanishes on the faces where the other two mass factors would act
+    (the identity the library's H-stage line rounds rest on); with a
+    varying permeability it does not."""
+    rng = np.random.default_rng(7)
+    Ns = maxwell.axis_counts(N)
+    shape = (Ns[2] + p, Ns[1] + p, Ns[0] + p)
+    eps = rng.uniform(1, 40, shape)
+    sig = rng.uniform(0, 5, shape)
+    for mu, same in ((1.7, True), (rng.uniform(0.5, 2.0, shape), False)):
+        prob = maxwell.Problem(N, p, eps, mu, sig, 0.07)
+        F = [rng.standard_normal(shape) for _ in range(9)]
+        E, H = prob.constrain(F[0:3], F[3:6])
+        En, _ = prob.constrain(F[6:9], F[3:6])
+        for sub in (1, 2):
+            fields = {"E1": E[0], "E2": E[1], "E3": E[2], "H1": H[0], "H2": H[1], "H3": H[2],
+                      "E1'": En[0], "E2'": En[1], "E3'": En[2]}
+            for c in range(3):
+                full = prob.solve3(prob.rhs_H(sub, fields, c), "H", c, None)
+                short = _h_by_line_operators(prob, sub, fields, c)
+                err = np.linalg.norm(short - full) / np.linalg.norm(full)
+                if same:
+                    assert err < 1e-12, (sub, c, err)
+                else:
+                    assert err > 1e-4, (sub, c, err)
