@@ -156,7 +156,9 @@ int adi_set_pivot_floor(adi_ctx* ctx, double floor);
  * residual correction of each stage's float32 solve of the three 1D
  * systems of section "Incorporating non-regular material data" (the
  * precision split is this library's, not the paper's).  Default
- * ADI_RES64_DEFAULT.
+ * ADI_RES64_DEFAULT.  With one permeability in every row the H stages run
+ * as apply-and-solve lines without a right-hand-side kernel, and their bits
+ * have no effect.
  * Ignored in ADI_FP64 mode.  Takes effect at the next adi_factor (the
  * context is unfactored until then).  EINVAL for a mask outside 0..15.
  */
