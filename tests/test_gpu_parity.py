@@ -394,8 +394,8 @@ def test_configured_lengths_fp32_against_fp64(Solver, name, steps):
     element-wise 5e-5 of the field's largest value.  At the end of the 128^3 run H
     has fallen to a ninth of its peak (the pulse is over) and H1, the
     component the x-directed dipole drives least, to 3 % of it: relative to
-    their own final norms the H components then differ by 8e-5 to 2.7e-4
-    (E: 3e-6), which is printed and bounded at 5e-4."""
+    their own final norms the H components then differ by 4e-5 to 1.5e-4
+    (E: 4e-6), which is printed and bounded at 5e-4."""
     cps = [steps // 4, steps // 2, 3 * steps // 4, steps]
     r32 = _run_gpu_workload(Solver, name, "fp32_refine", cps)
     r64 = _run_gpu_workload(Solver, name, "fp64", cps)
