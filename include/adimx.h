@@ -225,11 +225,12 @@ int adi_sync(adi_ctx* ctx);
  * launch's duration (the state advances by nsteps steps).  adi_profile_read
  * reports, for each launch of a step in launch order: its kind (0 = E
  * right-hand side, 1 = H right-hand side, 3 = x-line solves, 4 = y/z-line
- * solves, 5 = x- and y/z-line solves of one round in one launch), the
- * number of field components it processes, how many of those use per-line
- * (material-modified) factors, how many add the old state to their solution
- * (the last solves of the float32 mode), and its mean duration in
- * milliseconds.  *nout receives the number of launches per step
+ * solves, 5 = x- and y/z-line solves of one round in one launch, 6 = the
+ * H stage's apply-and-solve lines with one permeability), the number of
+ * field components it processes, how many of those use per-line
+ * (material-modified) factors, how many add a base state to their solution
+ * (the last solves of the float32 mode, the apply-and-solve lines), and its
+ * mean duration in milliseconds.  *nout receives the number of launches per step
  * (the arrays hold cap entries).
  */
 int adi_profile_run(adi_ctx* ctx, int nsteps);

@@ -239,7 +239,8 @@ int pick_zchunk(const int* ns) {
 }
 
 // ---------------------------------------------------------------- enqueue
-enum LaunchKind { kKindRhsE = 0, kKindRhsH = 1, kKindResidual = 2, kKindSweepX = 3, kKindSweepYZ = 4,
+// (kind 2 is not used: it named a separate float64 residual kernel)
+enum LaunchKind { kKindRhsE = 0, kKindRhsH = 1, kKindSweepX = 3, kKindSweepYZ = 4,
                   kKindSweepXYZ = 5, kKindApply = 6 };
 
 // Run `launch` on stream s; when profiling, bracket it with two events.

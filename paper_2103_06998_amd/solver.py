@@ -144,7 +144,7 @@ class Solver:
         return ptr.value, ("float64" if dt.value == 0 else "float32")
 
     # -- per-kernel timing -----------------------------------------------------
-    KINDS = ("rhs_E", "rhs_H", "residual64", "sweep_x", "sweep_yz", "sweep_xyz", "apply_xyz")
+    KINDS = ("rhs_E", "rhs_H", "unused", "sweep_x", "sweep_yz", "sweep_xyz", "apply_xyz")
 
     def profile(self, nsteps: int):
         """Run nsteps eager steps with HIP events around every launch."""
