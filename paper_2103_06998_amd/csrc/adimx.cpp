@@ -56,6 +56,7 @@ struct adi_ctx {
   hipStream_t stream = nullptr;
   hipStream_t cap = nullptr;
   hipStream_t side = nullptr;        // second branch of a step: x-line sweeps beside y/z
+  hipStream_t hside = nullptr;       // third branch: the H stage's first round beside the E stage
   std::vector<hipEvent_t> fork_ev;   // fork / join events of the branches
   size_t fork_idx = 0;
   std::string err;
@@ -340,6 +341,14 @@ size_t line_blocks(const adi_ctx* c, const SweepDesc* d, int nd) {
   return b;
 }
 
+// Blocks of 64 lines of one H-stage apply-and-solve round (one descriptor
+// per axis).
+size_t h_round_blocks(const adi_ctx* c) {
+  size_t b = 0;
+  for (int ax = 0; ax < 3; ++ax) b = std::max(b, (c->D / size_t(c->ns[ax]) + 63) / 64);
+  return 3 * b;
+}
+
 // Solve order of component c: modified axis first for E, x y z for H.
 void axis_order(int kindH, int sub, int c, int order[3]) {
   if (kindH) {
@@ -457,10 +466,14 @@ hipError_t enqueue_solves(adi_ctx* c, int kindH, int sub, void* buf, const void*
 //   H_c' = H_c + sum over the two terms of (+-delta) M_a^{-1} (A_a E_b).
 // Two rounds of apply-and-solve line launches (one term per component each,
 // the three components on three different axes) replace the right-hand
-// side kernel and the three rounds of mass solves.
+// side kernel and the three rounds of mass solves.  Round k = 0 takes the
+// terms on the E before the stage (Ein, added to Hin), round 1 those on the
+// E after it (added in place); this enqueues round k on stream s.  A round
+// too large for one launch puts its x lines on the side stream when
+// `may_branch`.
 template <typename T>
-hipError_t enqueue_h_fast(adi_ctx* c, int sub, void* Ein, void* Eout, void* Hin, void* Hout,
-                          hipStream_t s) {
+hipError_t enqueue_h_round(adi_ctx* c, int sub, int k, void* Ein, void* Eout, void* Hin,
+                           void* Hout, hipStream_t s, bool may_branch) {
   struct Term { int axis, sign, b; bool old; };  // b = E component, old = E before the stage
   static const Term terms[2][3][2] = {
       {{{1, -1, 2, true}, {2, +1, 1, false}},
@@ -470,70 +483,63 @@ hipError_t enqueue_h_fast(adi_ctx* c, int sub, void* Ein, void* Eout, void* Hin,
        {{0, +1, 2, true}, {2, -1, 0, false}},
        {{1, +1, 0, true}, {0, -1, 1, false}}}};
   const int W = 2 * c->p + 1;
-  for (int k = 0; k < 2; ++k) {
-    SweepDesc d[3];
-    for (int ci = 0; ci < 3; ++ci) {
-      const Term& t = terms[sub - 1][ci][k];
-      const int ax = t.axis, n = c->ns[ax];
-      void* io = comp(Hout, ci, c);
-      SweepDesc q = desc_for(c, 1, sub, ci, ax, comp(t.old ? Ein : Eout, t.b, c), io,
-                             k == 0 ? comp(Hin, ci, c) : io);
-      q.aband = static_cast<const T*>(c->bandT[ax]) + size_t(1) * n * W;  // op 1 = A
-      q.scale = t.sign * c->hdelta;
-      d[ax] = q;  // one term per axis in each round
-    }
-    SweepArgs a{};
-    for (int q = 0; q < 3; ++q) a.d[q] = d[q];  // x descriptor first
-    for (int q = 0; q < 3; ++q) a.dim[q] = c->ns[q];
-    a.apply = 1;
-    a.xaxis = 2;
-    a.spike = spike_for(a, 3);
-    if (!a.spike) return hipErrorInvalidValue;
-    if (sub == 2 && k == 1) {
-      a.tick_t = c->d_t;
-      a.tick_dt = c->dt;
-    }
-    const size_t blocks = line_blocks(c, a.d, 3) * 3;
-    if (blocks <= 1024) {
-      hipError_t e = timed(c, s, kKindApply, 3, 0, 3,
-                           [&] { return launch_sweep<T>(c->p, 3, a, s); });
-      if (e != hipSuccess) return e;
-      continue;
-    }
-    // larger rounds: the x lines on the side branch, the y/z lines here
-    SweepArgs ax_{}, ayz{};
-    ax_.d[0] = d[0];
-    ayz.d[0] = d[1];
-    ayz.d[1] = d[2];
-    for (SweepArgs* g : {&ax_, &ayz}) {
-      for (int q = 0; q < 3; ++q) g->dim[q] = c->ns[q];
-      g->apply = 1;
-    }
-    ax_.xaxis = 1;
-    ayz.xaxis = 0;
-    ax_.spike = spike_for(ax_, 1);
-    ayz.spike = spike_for(ayz, 2);
-    ayz.tick_t = a.tick_t;
-    ayz.tick_dt = a.tick_dt;
-    const bool branch = !c->profiling && c->side;
-    hipEvent_t ev = nullptr;
-    if (branch) {
-      hipError_t e = next_event(c, &ev);
-      if (e == hipSuccess) e = hipEventRecord(ev, s);
-      if (e == hipSuccess) e = hipStreamWaitEvent(c->side, ev, 0);
-      if (e != hipSuccess) return e;
-    }
-    hipStream_t xs = branch ? c->side : s;
-    hipError_t e = timed(c, xs, kKindApply, 1, 0, 1, [&] { return launch_sweep<T>(c->p, 1, ax_, xs); });
-    if (e == hipSuccess)
-      e = timed(c, s, kKindApply, 2, 0, 2, [&] { return launch_sweep<T>(c->p, 2, ayz, s); });
+  SweepDesc d[3];
+  for (int ci = 0; ci < 3; ++ci) {
+    const Term& t = terms[sub - 1][ci][k];
+    const int ax = t.axis, n = c->ns[ax];
+    void* io = comp(Hout, ci, c);
+    SweepDesc q = desc_for(c, 1, sub, ci, ax, comp(t.old ? Ein : Eout, t.b, c), io,
+                           k == 0 ? comp(Hin, ci, c) : io);
+    q.aband = static_cast<const T*>(c->bandT[ax]) + size_t(1) * n * W;  // op 1 = A
+    q.scale = t.sign * c->hdelta;
+    d[ax] = q;  // one term per axis in each round
+  }
+  SweepArgs a{};
+  for (int q = 0; q < 3; ++q) a.d[q] = d[q];  // x descriptor first
+  for (int q = 0; q < 3; ++q) a.dim[q] = c->ns[q];
+  a.apply = 1;
+  a.xaxis = 2;
+  a.spike = spike_for(a, 3);
+  if (!a.spike) return hipErrorInvalidValue;
+  if (sub == 2 && k == 1) {
+    a.tick_t = c->d_t;
+    a.tick_dt = c->dt;
+  }
+  if (h_round_blocks(c) <= 1024)
+    return timed(c, s, kKindApply, 3, 0, 3, [&] { return launch_sweep<T>(c->p, 3, a, s); });
+  // larger rounds: the x lines on the side branch, the y/z lines here
+  SweepArgs ax_{}, ayz{};
+  ax_.d[0] = d[0];
+  ayz.d[0] = d[1];
+  ayz.d[1] = d[2];
+  for (SweepArgs* g : {&ax_, &ayz}) {
+    for (int q = 0; q < 3; ++q) g->dim[q] = c->ns[q];
+    g->apply = 1;
+  }
+  ax_.xaxis = 1;
+  ayz.xaxis = 0;
+  ax_.spike = spike_for(ax_, 1);
+  ayz.spike = spike_for(ayz, 2);
+  ayz.tick_t = a.tick_t;
+  ayz.tick_dt = a.tick_dt;
+  const bool branch = may_branch && !c->profiling && c->side;
+  hipEvent_t ev = nullptr;
+  if (branch) {
+    hipError_t e = next_event(c, &ev);
+    if (e == hipSuccess) e = hipEventRecord(ev, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(c->side, ev, 0);
     if (e != hipSuccess) return e;
-    if (branch) {
-      e = next_event(c, &ev);
-      if (e == hipSuccess) e = hipEventRecord(ev, c->side);
-      if (e == hipSuccess) e = hipStreamWaitEvent(s, ev, 0);
-      if (e != hipSuccess) return e;
-    }
+  }
+  hipStream_t xs = branch ? c->side : s;
+  hipError_t e = timed(c, xs, kKindApply, 1, 0, 1, [&] { return launch_sweep<T>(c->p, 1, ax_, xs); });
+  if (e == hipSuccess)
+    e = timed(c, s, kKindApply, 2, 0, 2, [&] { return launch_sweep<T>(c->p, 2, ayz, s); });
+  if (e != hipSuccess) return e;
+  if (branch) {
+    e = next_event(c, &ev);
+    if (e == hipSuccess) e = hipEventRecord(ev, c->side);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, ev, 0);
+    if (e != hipSuccess) return e;
   }
   return hipSuccess;
 }
@@ -547,6 +553,16 @@ hipError_t enqueue_step_t(adi_ctx* c, hipStream_t s) {
     void* Hin = sub == 1 ? B[1] : B[3];
     void* Eout = sub == 1 ? B[2] : B[0];
     void* Hout = sub == 1 ? B[3] : B[1];
+    // With one permeability the H stage's first round reads only the
+    // substep's inputs (Ein, Hin) and writes only Hout, which the E stage
+    // neither reads nor writes: outside the profiling pass, a round too
+    // large for one launch runs on a branch of its own beside the E stage's
+    // solves, joined before round 2 (256^3 p=2 float64 step 6.55 -> 6.33 ms).
+    // At 128^3 the overlap gains nothing: the two kernels share the memory
+    // system (per-line sweep 67 -> 87 us, round 67 us instead of 37) and the
+    // fork and the join each leave the GPU idle for 5-10 us.
+    const bool hbranch = c->fast_h && !c->profiling && c->hside && h_round_blocks(c) > 1024;
+    hipEvent_t hev = nullptr;
     // E stage: right-hand sides (float32 mode: increments b - P E_old) into
     // Eout, then the three solves in place (float32 mode: + E_old)
     {
@@ -575,12 +591,23 @@ hipError_t enqueue_step_t(adi_ctx* c, hipStream_t s) {
         }
       }
       if (e != hipSuccess) return e;
+      if (hbranch) {
+        e = next_event(c, &hev);
+        if (e == hipSuccess) e = hipEventRecord(hev, s);
+        if (e == hipSuccess) e = hipStreamWaitEvent(c->hside, hev, 0);
+        if (e == hipSuccess) e = enqueue_h_round<T>(c, sub, 0, Ein, Eout, Hin, Hout, c->hside, false);
+        if (e == hipSuccess) e = next_event(c, &hev);
+        if (e == hipSuccess) e = hipEventRecord(hev, c->hside);
+        if (e != hipSuccess) return e;
+      }
       e = enqueue_solves<T>(c, 0, sub, Eout, c->refine() ? Ein : nullptr, s);
       if (e != hipSuccess) return e;
     }
     // H stage
     if (c->fast_h) {
-      hipError_t e = enqueue_h_fast<T>(c, sub, Ein, Eout, Hin, Hout, s);
+      hipError_t e = hbranch ? hipStreamWaitEvent(s, hev, 0)
+                             : enqueue_h_round<T>(c, sub, 0, Ein, Eout, Hin, Hout, s, true);
+      if (e == hipSuccess) e = enqueue_h_round<T>(c, sub, 1, Ein, Eout, Hin, Hout, s, true);
       if (e != hipSuccess) return e;
     } else {
       const void* f[9] = {comp(Hin, 0, c),  comp(Hin, 1, c),  comp(Hin, 2, c),
@@ -669,6 +696,7 @@ int ensure_stream(adi_ctx* c) {
   if (c->cap) return ADI_OK;
   HIPCHK(c, hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
   HIPCHK(c, hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+  HIPCHK(c, hipStreamCreateWithFlags(&c->hside, hipStreamNonBlocking));
   return ADI_OK;
 }
 
@@ -1226,6 +1254,7 @@ void adi_destroy(adi_ctx* c) {
   if (c->mms_part) hipFree(c->mms_part);
   if (c->cap) hipStreamDestroy(c->cap);
   if (c->side) hipStreamDestroy(c->side);
+  if (c->hside) hipStreamDestroy(c->hside);
   for (hipEvent_t e : c->fork_ev) hipEventDestroy(e);
   delete c;
 }
