@@ -91,6 +91,9 @@ struct adi_ctx {
   double* band64[3] = {};   // same in float64
   void* zwT = nullptr;      // z weights [M,A,B,S][k][2p+1] in the field type
   double* zw64 = nullptr;   // same in float64
+  // rows yin[0]..yin[1] of the y operators' bands equal row yin[2]
+  // (translation-invariant interior rows of uniform knots)
+  int yin[3] = {1, 0, 0};
   double* fb64[3] = {};     // per axis, factor bands: Mdir, Sdir (n_a (2p+1) each)
   // shared factors per axis: [axis][0] free, [axis][1] Dirichlet
   void* shL[3][2] = {}, *shU[3][2] = {}, *shD[3][2] = {};
@@ -215,6 +218,32 @@ int upload(adi_ctx* c, void* dst, const std::vector<double>& src) {
   return ADI_OK;
 }
 
+// The widest run of rows around the middle row of a 1D operator set
+// ([op][r][W], four operators) whose band rows all equal the middle row's to
+// within a relative 1e-14 of its largest entry (with uniform knots, the rows
+// whose basis functions and neighbours are all interior translates):
+// out = {first, last, middle}, or an empty range {1, 0, middle}.
+void invariant_rows(const std::vector<double>& ops, int n, int W, int out[3]) {
+  const int m = n / 2;
+  auto same = [&](int r) {
+    for (int op = 0; op < 4; ++op) {
+      const double* a = &ops[(size_t(op) * n + r) * W];
+      const double* b = &ops[(size_t(op) * n + m) * W];
+      double big = 0.0;
+      for (int d = 0; d < W; ++d) big = std::max(big, std::fabs(b[d]));
+      for (int d = 0; d < W; ++d)
+        if (std::fabs(a[d] - b[d]) > 1e-14 * big) return false;
+    }
+    return true;
+  };
+  int lo = m, hi = m;
+  while (lo > 0 && same(lo - 1)) --lo;
+  while (hi < n - 1 && same(hi + 1)) ++hi;
+  out[0] = lo;
+  out[1] = hi;
+  out[2] = m;
+}
+
 // Output planes per RHS block: the grid is 3 ceil(nx/32) ceil(ny/8)
 // ceil(nz/zchunk) blocks of 256 threads (one per tile and output component),
 // about two resident per CU; pick the chunk (>= 8 planes, to bound the
@@ -292,6 +321,9 @@ RhsArgs<T> rhs_args(adi_ctx* c, const void* const* f, int nf, void* const* out, 
   a.nx = c->ns[0];
   a.ny = c->ns[1];
   a.nz = c->ns[2];
+  a.yin0 = c->yin[0];
+  a.yin1 = c->yin[1];
+  a.yrep = c->yin[2];
   a.zchunk = pick_zchunk(c->ns);
   a.src = c->src;
   a.tnow = c->d_t;
@@ -965,6 +997,7 @@ int adi_factor(adi_ctx* c, double dt) {
     std::copy(g.S.begin(), g.S.end(), ops.begin() + size_t(3) * n * W);
     if ((st = upload(c, c->bandT[ax], ops)) != ADI_OK) return st;
     HIPCHK(c, hipMemcpy(c->band64[ax], ops.data(), ops.size() * 8, hipMemcpyHostToDevice));
+    if (ax == 1) invariant_rows(ops, n, W, c->yin);
     if (ax == 2) {
       // z weights: input plane k contributes Z[k-p+q][k] to output plane k-p+q
       std::vector<double> zw(size_t(4) * n * W, 0.0);

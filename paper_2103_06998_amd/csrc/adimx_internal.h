@@ -88,6 +88,8 @@ struct RhsArgs {
   const T* zw;            // z axis: [op][k][2p+1]: weight of input plane k on output
                           // plane k - p + q (band entry Z[k-p+q][k], zero outside)
   int nx, ny, nz;         // coefficients per axis
+  int yin0, yin1;         // rows yin0..yin1 of every y operator equal row yrep
+  int yrep;               // (translation-invariant interior rows; empty if yin0 > yin1)
   int zchunk;             // output planes per block
   SourceArgs src;
   const double* tnow;     // device time at the start of the step

@@ -145,6 +145,19 @@ __device__ __forceinline__ void static_for(F&& f) {
   static_for_impl<N>(f, std::make_integer_sequence<int, N>{});
 }
 
+// A value the same in every lane of the wave, held in scalar registers.
+template <typename T>
+__device__ __forceinline__ T wave_uniform(T v) {
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
+  } else {
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = unsigned(__builtin_amdgcn_readfirstlane(int(unsigned(u))));
+    const unsigned hi = unsigned(__builtin_amdgcn_readfirstlane(int(unsigned(u >> 32))));
+    return __builtin_bit_cast(T, (static_cast<unsigned long long>(hi) << 32) | lo);
+  }
+}
+
 constexpr int kTX = 32, kTY = 8, kCols = kTX * kTY;
 constexpr int kXcds = 8;  // MI355X: 8 accelerator complex dies, one L2 each
 constexpr int kRhsThreads = kCols;  // one block per (tile, output component)
@@ -249,6 +262,16 @@ __device__ __forceinline__ void rhs_tile(const RhsArgs<TC>& a, const TC* __restr
   const int nsp = on ? CT.nsp[comp][slot] : 0;  // pairs of this wave's field
   const int pr0 = CT.spair[comp][slot][0], pr1 = CT.spair[comp][slot][1];
   const int yop0 = CT.pyop[comp][pr0], yop1 = CT.pyop[comp][pr1];
+  // A tile whose output rows all have the band rows of row yrep (interior
+  // rows of uniform knots) takes the wave's y weights from scalar registers
+  // instead of reading 8 band rows per operator from LDS on every plane.
+  const bool yin = j0 >= a.yin0 && j0 + kTY - 1 <= a.yin1;
+  TC wy0[W], wy1[W];
+#pragma unroll
+  for (int d = 0; d < W; ++d) {
+    wy0[d] = wave_uniform(bandy[(size_t(wave_uniform(yop0)) * ny + a.yrep) * W + d]);
+    wy1[d] = wave_uniform(bandy[(size_t(wave_uniform(yop1)) * ny + a.yrep) * W + d]);
+  }
   // Addresses are a block-uniform row or plane pointer plus a 32-bit lane
   // offset (nx ny < 2^31), which keeps one offset register per lane.
   const TI* fsrc = static_cast<const TI*>(a.f[CT.field[comp][slot]]);
@@ -341,7 +364,24 @@ __device__ __forceinline__ void rhs_tile(const RhsArgs<TC>& a, const TC* __restr
     load_cf(te + 1, cfr[S ^ 1]);
     TC* G = sG + S * GSZ;
     // y pass from registers: the wave's one or two y operators on its field
-    if (on && lane < HX) {
+    if (on && lane < HX && yin) {
+#pragma unroll
+      for (int yy = 0; yy < kTY; ++yy) {
+        TC s = TC(0);
+#pragma unroll
+        for (int d = 0; d < W; ++d) s += wy0[d] * TC(pre[S][yy + d]);
+        G[(pr0 * kTY + yy) * HX + lane] = s;
+      }
+      if (CT.maxsp > 1 && nsp > 1) {  // wave-uniform
+#pragma unroll
+        for (int yy = 0; yy < kTY; ++yy) {
+          TC s = TC(0);
+#pragma unroll
+          for (int d = 0; d < W; ++d) s += wy1[d] * TC(pre[S][yy + d]);
+          G[(pr1 * kTY + yy) * HX + lane] = s;
+        }
+      }
+    } else if (on && lane < HX) {
       const TC* yb0 = sYB + yop0 * kTY * W;
 #pragma unroll
       for (int yy = 0; yy < kTY; ++yy) {
