@@ -1161,6 +1161,20 @@ __device__ __forceinline__ void spike_body(const SweepArgs& a) {
     for (int r = 0; r < MR; ++r) y[r] *= sc;
   }
   if (XAX) {
+    // the values to add (x_old) in the stores' own pattern, every chunk's
+    // loads in flight at once (rows and lines clamped) instead of one wait
+    // per chunk
+    constexpr int NCS = (MR + 7) / 8;
+    T av[NCS][8];
+    if (accp) {  // uniform
+#pragma unroll
+      for (int c = 0; c < NCS; ++c)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int e = lane + 64 * j, ln = e >> 3, rr = e & 7;
+          av[c][j] = accp[size_t(min(l0 + ln, nl - 1)) * n + b0 + min(8 * c + rr, m - 1)];
+        }
+    }
 #pragma unroll
     for (int c0 = 0; c0 < MR; c0 += 8) {
       if (c0 < m) {  // uniform
@@ -1174,7 +1188,7 @@ __device__ __forceinline__ void spike_body(const SweepArgs& a) {
           if (l0 + ln < nl && c0 + rr < m) {
             const size_t o = size_t(l0 + ln) * n + b0 + c0 + rr;
             T x = xt[rr * 65 + ln];
-            if (accp) x += accp[o];
+            if (accp) x += av[c0 / 8][j];
             out[o] = x;
           }
         }
