@@ -22,7 +22,11 @@ constexpr int HXX = TX + 2, HYY = TY + 2, HZZ = TZ + 2;
 constexpr int HV = HXX * HYY * HZZ;     // staged voxels (648)
 constexpr int kThreads = 256;
 
-__device__ __forceinline__ float sigmoid_f(float z) { return 1.0f / (1.0f + __expf(-z)); }
+// The hardware reciprocal (1 ulp) instead of a correctly rounded division:
+// the activations are rounded to bfloat16 (8 bits) right after.
+__device__ __forceinline__ float sigmoid_f(float z) {
+  return __builtin_amdgcn_rcpf(1.0f + __expf(-z));
+}
 __device__ __forceinline__ float silu_f(float z) { return z * sigmoid_f(z); }
 __device__ __forceinline__ float silu_grad_f(float z) {
   const float s = sigmoid_f(z);
@@ -71,6 +75,12 @@ __global__ __launch_bounds__(kThreads) void conv_kernel(ConvArgs a) {
 #pragma unroll
     for (int j = 0; j < NT; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
+  // Fully unrolled: each step's tap and channel offsets are then constants
+  // (with 32 input channels a step is exactly one tap), so the LDS and
+  // weight addresses take immediate offsets instead of a division chain per
+  // step, and the zero fill of lanes past the last tap is folded away where
+  // K is a multiple of 32.
+#pragma unroll
   for (int ks = 0; ks < NK; ++ks) {
     const int k0 = ks * 32 + g * 8;  // this lane's 8 consecutive k
     const int t = k0 / CI, c0 = k0 % CI;
