@@ -57,14 +57,31 @@ __global__ __launch_bounds__(kThreads) void conv_kernel(ConvArgs a) {
   const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, z0 = blockIdx.z * TZ;
   const __bf16* in = a.in;
 
-  for (int idx = tid; idx < HV * CH; idx += kThreads) {
+  // Stage the halo tile: every thread's loads are issued before any is
+  // used (from addresses clamped into the grid), then voxels outside the
+  // grid are zeroed as the values go to LDS, so the loads are in flight
+  // together instead of one load-then-store round trip per chunk.
+  constexpr int NST = HV * CH, NIT = (NST + kThreads - 1) / kThreads;
+  bf16x8 sv[NIT];
+  bool inb[NIT];
+#pragma unroll
+  for (int it = 0; it < NIT; ++it) {
+    const int idx = min(tid + it * kThreads, NST - 1);
     const int v = idx / CH, c = idx % CH;
     const int hx = v % HXX, hy = (v / HXX) % HYY, hz = v / (HXX * HYY);
     const int gx = x0 - 1 + hx, gy = y0 - 1 + hy, gz = z0 - 1 + hz;
-    bf16x8 val = zero8();
-    if (gx >= 0 && gx < nx && gy >= 0 && gy < ny && gz >= 0 && gz < nz)
-      val = *reinterpret_cast<const bf16x8*>(in + ((size_t(gz) * ny + gy) * nx + gx) * CI + c * 8);
-    *reinterpret_cast<bf16x8*>(tile + v * PIT + c * 8) = val;
+    inb[it] = gx >= 0 && gx < nx && gy >= 0 && gy < ny && gz >= 0 && gz < nz;
+    const int cx = min(max(gx, 0), nx - 1), cy = min(max(gy, 0), ny - 1),
+              cz = min(max(gz, 0), nz - 1);
+    sv[it] = *reinterpret_cast<const bf16x8*>(in + ((size_t(cz) * ny + cy) * nx + cx) * CI + c * 8);
+  }
+#pragma unroll
+  for (int it = 0; it < NIT; ++it) {
+    const int idx = tid + it * kThreads;
+    if (idx < NST) {
+      const int v = idx / CH, c = idx % CH;
+      *reinterpret_cast<bf16x8*>(tile + v * PIT + c * 8) = inb[it] ? sv[it] : zero8();
+    }
   }
   __syncthreads();
 
