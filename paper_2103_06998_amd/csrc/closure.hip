@@ -166,25 +166,53 @@ __global__ __launch_bounds__(kThreads) void wgrad_kernel(WgradArgs a) {
   const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, z0 = blockIdx.z * TZ;
   const size_t blk = (size_t(blockIdx.z) * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
 
-  for (int idx = tid; idx < HV * (CI / 8); idx += kThreads) {
+  // Both operands staged channel-major; as in the forward kernel, every
+  // load of a thread is issued (from addresses clamped into the grid) before
+  // the values are zeroed outside the grid and written to LDS.
+  constexpr int NX8 = HV * (CI / 8), NXI = (NX8 + kThreads - 1) / kThreads;
+  constexpr int ND8 = NV * (COP / 8), NDI = (ND8 + kThreads - 1) / kThreads;
+  bf16x8 xv[NXI], dv[NDI];
+  bool xin[NXI], din[NDI];
+#pragma unroll
+  for (int it = 0; it < NXI; ++it) {
+    const int idx = min(tid + it * kThreads, NX8 - 1);
     const int v = idx / (CI / 8), c = idx % (CI / 8);
     const int hx = v % HXX, hy = (v / HXX) % HYY, hz = v / (HXX * HYY);
     const int gx = x0 - 1 + hx, gy = y0 - 1 + hy, gz = z0 - 1 + hz;
-    bf16x8 val = zero8();
-    if (gx >= 0 && gx < nx && gy >= 0 && gy < ny && gz >= 0 && gz < nz)
-      val = *reinterpret_cast<const bf16x8*>(a.in + ((size_t(gz) * ny + gy) * nx + gx) * CI + c * 8);
-#pragma unroll
-    for (int j = 0; j < 8; ++j) X[(c * 8 + j) * HV + v] = val[j];
+    xin[it] = gx >= 0 && gx < nx && gy >= 0 && gy < ny && gz >= 0 && gz < nz;
+    const int cx = min(max(gx, 0), nx - 1), cy = min(max(gy, 0), ny - 1),
+              cz = min(max(gz, 0), nz - 1);
+    xv[it] = *reinterpret_cast<const bf16x8*>(a.in + ((size_t(cz) * ny + cy) * nx + cx) * CI + c * 8);
   }
-  for (int idx = tid; idx < NV * (COP / 8); idx += kThreads) {
+#pragma unroll
+  for (int it = 0; it < NDI; ++it) {
+    const int idx = min(tid + it * kThreads, ND8 - 1);
     const int v = idx / (COP / 8), c = idx % (COP / 8);
     const int lx = v % TX, ly = (v / TX) % TY, lz = v / (TX * TY);
     const int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
-    bf16x8 val = zero8();
-    if (gx < nx && gy < ny && gz < nz)
-      val = *reinterpret_cast<const bf16x8*>(a.dz + ((size_t(gz) * ny + gy) * nx + gx) * COP + c * 8);
+    din[it] = gx < nx && gy < ny && gz < nz;
+    const int cx = min(gx, nx - 1), cy = min(gy, ny - 1), cz = min(gz, nz - 1);
+    dv[it] = *reinterpret_cast<const bf16x8*>(a.dz + ((size_t(cz) * ny + cy) * nx + cx) * COP + c * 8);
+  }
 #pragma unroll
-    for (int j = 0; j < 8; ++j) Dz[(c * 8 + j) * DP + v] = val[j];
+  for (int it = 0; it < NXI; ++it) {
+    const int idx = tid + it * kThreads;
+    if (idx < NX8) {
+      const int v = idx / (CI / 8), c = idx % (CI / 8);
+      const bf16x8 val = xin[it] ? xv[it] : zero8();
+#pragma unroll
+      for (int j = 0; j < 8; ++j) X[(c * 8 + j) * HV + v] = val[j];
+    }
+  }
+#pragma unroll
+  for (int it = 0; it < NDI; ++it) {
+    const int idx = tid + it * kThreads;
+    if (idx < ND8) {
+      const int v = idx / (COP / 8), c = idx % (COP / 8);
+      const bf16x8 val = din[it] ? dv[it] : zero8();
+#pragma unroll
+      for (int j = 0; j < 8; ++j) Dz[(c * 8 + j) * DP + v] = val[j];
+    }
   }
   __syncthreads();
 
