@@ -121,28 +121,73 @@ __global__ __launch_bounds__(kThreads) void conv_kernel(ConvArgs a) {
   }
 
   const int gz = z0 + wave;
+  if constexpr (EPI == 1 || EPI == 3) {
+    // The bf16 activations leave through LDS (the staged tile is no longer
+    // read): each wave writes its TY x TX x COP outputs channels-last with a
+    // row pitch of COP + 4 values (the four 16-lane groups of a 2-byte write
+    // fall on disjoint banks), then each lane stores 8 channels of one voxel
+    // with one 16-byte write, 4 stores per wave instead of 32 per lane.
+    static_assert(COP == 32, "four lanes per voxel");
+    constexpr int OP = COP + 4;
+    static_assert(4 * TY * TX * OP <= HV * PIT, "fits in the staged tile");
+    typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
+    __syncthreads();  // every wave is done with the staged tile
+    __bf16* ob = tile + wave * (TY * TX * OP);
 #pragma unroll
-  for (int mt = 0; mt < TY; ++mt) {
-    const int gy = y0 + mt;
+    for (int mt = 0; mt < TY; ++mt) {
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) {
-      const int co = nt * 16 + m;
+      for (int nt = 0; nt < NT; ++nt) {
+        const int co = nt * 16 + m;
+        const float bco = a.bias[co];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int gx = x0 + 4 * g + r;
-        if (gx >= nx || gy >= ny || gz >= nz) continue;
-        const size_t v = (size_t(gz) * ny + gy) * nx + gx;
-        const float val = acc[mt][nt][r];
-        if (EPI == 0) {
-          if (co < a.co_real) a.out_f32[v * a.co_real + co] = val + a.bias[co];
-        } else if (EPI == 1) {
-          const float z = val + a.bias[co];
-          a.out_f32[v * COP + co] = z;
-          a.out_bf16[v * COP + co] = __bf16(silu_f(z));
-        } else if (EPI == 3) {
-          a.out_bf16[v * COP + co] = __bf16(silu_f(val + a.bias[co]));
-        } else {
-          a.out_bf16[v * COP + co] = __bf16(val * silu_grad_f(a.zprev[v * COP + co]));
+        for (int r = 0; r < 4; ++r) {
+          const int x = 4 * g + r;
+          const float z = acc[mt][nt][r] + bco;
+          if (EPI == 1) {
+            const int gx = x0 + x, gy = y0 + mt;
+            if (gx < nx && gy < ny && gz < nz)
+              a.out_f32[((size_t(gz) * ny + gy) * nx + gx) * COP + co] = z;
+          }
+          ob[(mt * TX + x) * OP + co] = __bf16(silu_f(z));
+        }
+      }
+    }
+    __syncthreads();
+    const int x = lane >> 2, q = lane & 3;  // voxel of the row, 8-channel chunk
+    const int gx = x0 + x;
+#pragma unroll
+    for (int mt = 0; mt < TY; ++mt) {
+      const int gy = y0 + mt;
+      const __bf16* src = ob + (mt * TX + x) * OP + q * 8;  // 8-byte aligned
+      const bf16x4 lo = *reinterpret_cast<const bf16x4*>(src);
+      const bf16x4 hi = *reinterpret_cast<const bf16x4*>(src + 4);
+      bf16x8 v8;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        v8[j] = lo[j];
+        v8[j + 4] = hi[j];
+      }
+      if (gx < nx && gy < ny && gz < nz)
+        *reinterpret_cast<bf16x8*>(a.out_bf16 + ((size_t(gz) * ny + gy) * nx + gx) * COP + q * 8) = v8;
+    }
+  } else {
+#pragma unroll
+    for (int mt = 0; mt < TY; ++mt) {
+      const int gy = y0 + mt;
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        const int co = nt * 16 + m;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int gx = x0 + 4 * g + r;
+          if (gx >= nx || gy >= ny || gz >= nz) continue;
+          const size_t v = (size_t(gz) * ny + gy) * nx + gx;
+          const float val = acc[mt][nt][r];
+          if (EPI == 0) {
+            if (co < a.co_real) a.out_f32[v * a.co_real + co] = val + a.bias[co];
+          } else {
+            a.out_bf16[v * COP + co] = __bf16(val * silu_grad_f(a.zprev[v * COP + co]));
+          }
         }
       }
     }
