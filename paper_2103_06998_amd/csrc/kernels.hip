@@ -243,9 +243,22 @@ __device__ __forceinline__ void rhs_tile(const RhsArgs<TC>& a, const TC* __restr
     const int op = idx / (kTY * W), rem = idx % (kTY * W), yy = rem / W, d = rem % W;
     sYB[idx] = bandy[(size_t(op) * ny + min(j0 + yy, ny - 1)) * W + d];
   }
-  for (int idx = tid; idx < (kend - kbeg) * 4 * W; idx += kRhsThreads) {
-    const int kk = idx / (4 * W), rem = idx % (4 * W), op = rem / W, q = rem % W;
-    sZW[idx] = zw[(size_t(op) * nz + kbeg + kk) * W + q];
+  // (four loads of a thread in flight before their LDS writes: one
+  // load-then-store round trip per value had delayed the plane loop's start)
+  {
+    const int nzw = (kend - kbeg) * 4 * W;
+    for (int base = tid; base < nzw; base += 4 * kRhsThreads) {
+      TC v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int idx = min(base + u * kRhsThreads, nzw - 1);
+        const int kk = idx / (4 * W), rem = idx % (4 * W), op = rem / W, q = rem % W;
+        v[u] = zw[(size_t(op) * nz + kbeg + kk) * W + q];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (base + u * kRhsThreads < nzw) sZW[base + u * kRhsThreads] = v[u];
+    }
   }
 
   // This wave's field slot (its one or two y operators) and this lane's
