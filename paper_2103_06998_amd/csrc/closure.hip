@@ -170,6 +170,32 @@ __global__ __launch_bounds__(kThreads) void conv_kernel(ConvArgs a) {
       if (gx < nx && gy < ny && gz < nz)
         *reinterpret_cast<bf16x8*>(a.out_bf16 + ((size_t(gz) * ny + gy) * nx + gx) * COP + q * 8) = v8;
     }
+  } else if constexpr (EPI == 0) {
+    // The network's outputs (co_real <= COP float32 channels per voxel) also
+    // leave through LDS: a row of TX voxels is co_real * TX consecutive
+    // floats in global memory, written by consecutive lanes.
+    static_assert(NT == 1, "one 16-channel tile");
+    static_assert(4 * TY * TX * COP * sizeof(float) <= HV * PIT * sizeof(__bf16),
+                  "fits in the staged tile");
+    const int cr = a.co_real;
+    __syncthreads();  // every wave is done with the staged tile
+    float* ob = reinterpret_cast<float*>(tile) + wave * (TY * TX * COP);
+    if (m < cr) {
+      const float bco = a.bias[m];
+#pragma unroll
+      for (int mt = 0; mt < TY; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) ob[(mt * TX + 4 * g + r) * cr + m] = acc[mt][0][r] + bco;
+    }
+    __syncthreads();
+    const int nvalid = max(0, min(TX, nx - x0)) * cr;  // floats of the row inside the grid
+#pragma unroll
+    for (int mt = 0; mt < TY; ++mt) {
+      const int gy = y0 + mt;
+      if (gy >= ny || gz >= nz) continue;
+      float* dst = a.out_f32 + ((size_t(gz) * ny + gy) * nx + x0) * cr;
+      for (int e = lane; e < nvalid; e += 64) dst[e] = ob[mt * TX * cr + e];
+    }
   } else {
 #pragma unroll
     for (int mt = 0; mt < TY; ++mt) {
@@ -182,12 +208,7 @@ __global__ __launch_bounds__(kThreads) void conv_kernel(ConvArgs a) {
           const int gx = x0 + 4 * g + r;
           if (gx >= nx || gy >= ny || gz >= nz) continue;
           const size_t v = (size_t(gz) * ny + gy) * nx + gx;
-          const float val = acc[mt][nt][r];
-          if (EPI == 0) {
-            if (co < a.co_real) a.out_f32[v * a.co_real + co] = val + a.bias[co];
-          } else {
-            a.out_bf16[v * COP + co] = __bf16(val * silu_grad_f(a.zprev[v * COP + co]));
-          }
+          a.out_bf16[v * COP + co] = __bf16(acc[mt][nt][r] * silu_grad_f(a.zprev[v * COP + co]));
         }
       }
     }
